@@ -1,0 +1,210 @@
+"""Throughput of the Teukolsky Lax-Wendroff step on one MI355X.
+
+A "step" is one full time step (stage lw1 then lw2) of the headline workload:
+s = -2, m = 2, a/M = 0.9 on 4096 r* x 128 theta, r* in [-200, 800] M, FP64,
+CFL 0.5.  value = grid-point updates per second (n_r * n_theta per step) over
+exactly --steps timed steps, inputs resident in HBM.  The same JSON line
+carries the double-double and quad-double workloads, the batched-vs-loop
+comparison, the roofline of the step kernel and the oracle timed on the host
+cores.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+
+# algorithmic bytes per grid-point update of the step kernel: state read
+# (4 reals) + state write (4 reals) + 16 stored coefficients (8 at the half
+# node, 8 at the node), each real `words` doubles
+def bytes_per_update(words):
+    return (4 + 4 + 16) * 8 * words
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    return torch
+
+
+def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream):
+    g = T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
+    h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
+    h.set_stream(stream.cuda_stream)
+    if tile:
+        h.set_tile(tile)
+    if graph:
+        h.use_graph(graph)
+    h.set_initial(*fields)
+    with torch.cuda.stream(stream):
+        h.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        h.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    finite = h.check_finite()
+    h.close()
+    return ms, wall, finite
+
+
+def cpu_baseline(w, seconds_target=12.0):
+    """The oracle (C fixed-point engine, all host cores) on a radial slab of the
+    headline workload: 512 r* nodes around the pulse x all theta rows."""
+    from paper_1006_0663_amd import inputs
+    from oracle import engine, problem
+    nslab = 512
+    full = inputs.initial_fields(w)
+    peak = int(abs(full[0][..., 0]).sum(axis=0).argmax())
+    i0 = max(0, min(w.n_r - nslab, peak - nslab // 2))
+    h = (w.rstar_max - w.rstar_min) / (w.n_r - 1)
+    # same spacing and time step as the full grid: dt = cfl*min(h, dtheta)
+    slab = problem.Problem(w.s, w.m, w.a_over_M, nslab, w.n_theta, w.rstar_min + i0 * h,
+                           w.rstar_min + (i0 + nslab - 1) * h, w.cfl)
+    cores = os.cpu_count() or 1
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    tab = problem.build_tables(slab, processes=min(cores, 16))
+    FT = engine.tables_to_fixed(tab, processes=min(cores, 16))
+    u = engine.fields_to_fixed([f[:, i0:i0 + nslab] for f in full])
+    t0 = time.perf_counter()
+    engine.run_fixed(FT, nslab, w.n_theta, u, 1, threads=cores)
+    one = time.perf_counter() - t0
+    nsteps = max(1, int(seconds_target / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    engine.run_fixed(FT, nslab, w.n_theta, u, nsteps, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": nslab * w.n_theta * nsteps / dt, "unit": "grid-point updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d steps of a %d x %d r*-slab (nodes %d..%d) of the headline grid, 384-bit fixed point, %.1f s"
+                      % (nsteps, nslab, w.n_theta, i0, i0 + nslab - 1, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--graph", type=int, default=100, help="steps per captured HIP graph (0 = plain launches)")
+    ap.add_argument("--tile", type=int, default=0, help="r* nodes per segment (0 = library default)")
+    ap.add_argument("--headline-only", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-instances", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the r*-slab decomposition across GPUs is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    torch = _torch()
+    from paper_1006_0663_amd import inputs, teuk as T
+    T.lib()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    w = inputs.C2
+    log("bench: generating %s inputs" % w.name)
+    fields = inputs.initial_fields(w)
+    log("bench: timing %s, %d warmup + %d steps" % (w.name, args.warmup, args.steps))
+    ms, wall, finite = time_single(T, w, fields, args.steps, args.warmup, args.graph, args.tile, torch, stream)
+    pts = w.n_r * w.n_theta
+    value = pts * args.steps / (ms / 1e3)
+    ms_step = ms / args.steps
+    achieved = bytes_per_update(1) * pts / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": "grid-point updates/sec per precision (FP64/dd/qd) + % FP64 peak; batched vs plain",
+        "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "teukolsky-lw fp64 s=-2 m=2 a/M=0.9 4096x128 r*[-200,800] cfl=0.5",
+                   "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "lw_step_kernel<double,128>",
+                     "algorithmic_bytes_per_update": bytes_per_update(1)},
+        "finite": finite,
+        "wall_s_timed": wall,
+    }
+    if not args.headline_only:
+        per = {"fp64": {"workload": w.name, "updates_per_s": value}}
+        for wx in (inputs.C3, inputs.C3_PARITY, inputs.C4):
+            log("bench: timing %s (%d steps)" % (wx.name, wx.steps))
+            fx = inputs.initial_fields(wx)
+            msx, _, fin = time_single(T, wx, fx, wx.steps, min(args.warmup, wx.steps // 10), args.graph,
+                                      args.tile, torch, stream)
+            per[wx.name] = {"workload": wx.name, "words": wx.words, "steps": wx.steps,
+                            "updates_per_s": wx.n_r * wx.n_theta * wx.steps / (msx / 1e3),
+                            "ms_per_step": msx / wx.steps, "finite": fin}
+        out["per_precision"] = per
+        out["batched"] = bench_batched(T, inputs, args, torch, stream, log)
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(T, inputs, args, torch, stream, log):
+    ws = inputs.batch_workloads(n=args.batch_instances)
+    steps = ws[0].steps
+    log("bench: batched %d dd instances x %d steps (generating inputs)" % (len(ws), steps))
+    fields = [inputs.initial_fields(w) for w in ws]
+    grids = [T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl) for w in ws]
+    b = T.TeukBatch([(w.s, w.m, w.a_over_M, g) for w, g in zip(ws, grids)], 2)
+    b.set_stream(stream.cuda_stream)
+    if args.graph:
+        b.use_graph(args.graph)
+    for k, f in enumerate(fields):
+        b.set_initial(k, *f)
+    pts = sum(w.n_r * w.n_theta for w in ws)
+    with torch.cuda.stream(stream):
+        b.step(min(args.warmup, 50))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    b.close()
+    log("bench: plain loop over the same instances")
+    hs = []
+    for w, g, f in zip(ws, grids, fields):
+        h = T.Teuk(w.s, w.m, w.a_over_M, g, 2)
+        h.set_stream(stream.cuda_stream)
+        if args.graph:
+            h.use_graph(args.graph)
+        h.set_initial(*f)
+        hs.append(h)
+    with torch.cuda.stream(stream):
+        for h in hs:
+            h.step(min(args.warmup, 50))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for h in hs:
+            h.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    for h in hs:
+        h.close()
+    return {"instances": len(ws), "steps": steps, "points": pts,
+            "batched_updates_per_s": pts * steps / (ms_b / 1e3),
+            "plain_loop_updates_per_s": pts * steps / (ms_p / 1e3),
+            "speedup": ms_p / ms_b}
+
+
+if __name__ == "__main__":
+    main()

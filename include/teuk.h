@@ -1,0 +1,162 @@
+/*
+ * libteuk -- the (2+1)D azimuthal-mode Teukolsky equation on a Kerr
+ * background, advanced by the two-step Lax-Wendroff scheme on MI355X (gfx950)
+ * in double, double-double or quad-double arithmetic.
+ *
+ * The problem is the one the paper states (Ginjupalli & Khanna, "High-Precision
+ * Numerical Simulations of Rotating Black Holes Accelerated by CUDA"):
+ *   - Eq. (1) (Sec. "Teukolsky Equation"): spin weight s, azimuthal number m,
+ *     mass M and spin a of the hole;
+ *   - Sec. "Teukolsky Code": tortoise coordinate r*, the ansatz
+ *     Psi = exp(i m phi~) r^3 Phi(t, r*, theta), the momentum
+ *     Pi = d_t Phi + b d_r* Phi, the first-order form Eq. (new_teu2) and its
+ *     Lax-Wendroff steps Eqs. (lw1)/(lw2); Phi = Pi = 0 on both radial
+ *     boundaries, and the pole condition by the parity of |m|;
+ *   - Sec. "High-Order and High-Precision": tenth-order angular derivatives
+ *     (second order is also offered) and the three precisions.
+ *
+ * Grid (readings of the paper, which states none of these):
+ *   r*_i = rstar_min + i h, h = (rstar_max - rstar_min)/(n_r - 1), i = 0..n_r-1
+ *     (both end nodes are the Dirichlet boundary);
+ *   theta_j = (j + 1/2) pi / n_theta, j = 0..n_theta-1 (cell centres; the pole
+ *     condition enters through reflected ghost rows of sign (-1)^|m|);
+ *   dt = cfl * min(h, pi / n_theta).
+ *
+ * Host field arrays ("interchange layout") are row-major [n_theta][n_r][p]
+ * doubles: theta row j, then r* node i (fastest over nodes), then the p words
+ * of one real (p = 1, 2 or 4, leading word first).  A p-word real is the exact
+ * sum of its words; inputs are taken as given and results are non-overlapping
+ * expansions.  The device layout is private to the library.
+ *
+ * Ownership: the library owns every handle and all device memory.  Host
+ * buffers belong to the caller and are only accessed during the call.
+ * Errors: every call returns TEUK_OK (0) or a negative code; the message of
+ * the last failure on the calling thread is returned by teuk_last_error().
+ * A failed device launch leaves the handle in a sticky TEUK_EDEVICE state.
+ * Argument validation happens on the host before any device work, so it needs
+ * no GPU.  Calls on one handle must not overlap; different handles are
+ * independent.
+ */
+#ifndef TEUK_H
+#define TEUK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TEUK_ABI_VERSION 1
+
+typedef enum { TEUK_FP64 = 1, TEUK_DD = 2, TEUK_QD = 4 } teuk_precision; /* value = words per real */
+typedef enum { TEUK_PHI_RE = 0, TEUK_PHI_IM = 1, TEUK_PI_RE = 2, TEUK_PI_IM = 3 } teuk_field;
+
+enum {
+    TEUK_OK = 0,
+    TEUK_EINVAL = -1,     /* invalid argument (checked on the host) */
+    TEUK_ENOMEM = -2,     /* device or host allocation failed */
+    TEUK_EDEVICE = -3,    /* HIP runtime or launch failure; sticky on the handle */
+    TEUK_ENOTSUP = -4,    /* valid request this build does not support */
+    TEUK_ENONFINITE = -5  /* a field holds Inf or NaN (teuk_check_finite) */
+};
+
+typedef struct {
+    int n_r;            /* r* nodes including both boundary nodes, >= 3 */
+    int n_theta;        /* theta cells, >= 5 */
+    double rstar_min;   /* units of M */
+    double rstar_max;   /* > rstar_min */
+    double cfl;         /* dt = cfl * min(h, pi/n_theta), > 0 */
+    double mass;        /* M: 1.0, or 0.0 for the flat-space test mode (a = 0, rstar_min > 0) */
+    int angular_order;  /* 10 (production, Sec. "High-Order and High-Precision") or 2 */
+} teuk_grid;
+
+typedef struct teuk teuk_t;
+typedef struct teuk_batch teuk_batch_t;
+
+/* ABI version and a short build description ("gfx950 ..."). */
+int teuk_abi_version(void);
+const char *teuk_build_info(void);
+/* Message of the last error on this thread ("" if none). */
+const char *teuk_last_error(void);
+
+/* Validate (s, m, a/M, grid, precision) without touching a device.
+ * |s| <= 2, |a/M| < 1, n_theta >= 5, n_r >= 3, rstar_min < rstar_max, cfl > 0,
+ * angular_order in {2, 10}, precision in {1, 2, 4}; mass must be 1.0, or 0.0
+ * with a/M = 0 and rstar_min > 0.  Returns TEUK_OK or TEUK_EINVAL. */
+int teuk_validate(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec);
+
+/* Create one instance on the current HIP device: allocates its state and
+ * coefficient arrays and runs the coefficient pass (tortoise inversion and
+ * the Kerr factors at working precision).  Fields start at zero.
+ * *out receives the handle; on failure *out is NULL. */
+int teuk_create(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec,
+                teuk_t **out);
+int teuk_destroy(teuk_t *h);
+
+/* Copy the four initial fields (interchange layout, n_theta*n_r*p doubles
+ * each) to the device; the radial boundary nodes are then set to zero and the
+ * step counter to 0.  Synchronous: the host buffers may be reused on return. */
+int teuk_set_initial(teuk_t *h, const double *phi_re, const double *phi_im, const double *pi_re,
+                     const double *pi_im);
+
+/* Advance n >= 0 full steps (lw1 then lw2 each).  Asynchronous on the
+ * handle's stream; no host round trip between steps. */
+int teuk_step(teuk_t *h, long n);
+
+/* Synchronise the handle's stream and copy one field out (interchange layout). */
+int teuk_read_field(teuk_t *h, teuk_field f, double *out);
+
+/* Time step (leading word), steps taken since set_initial, precision words. */
+double teuk_dt(const teuk_t *h);
+long teuk_steps_done(const teuk_t *h);
+int teuk_words(const teuk_t *h);
+/* Restore the step counter after a checkpoint restart (fields via set_initial). */
+int teuk_set_step_index(teuk_t *h, long n);
+
+/* Run subsequent work on the given hipStream_t (0 = the library's own stream). */
+int teuk_set_stream(teuk_t *h, void *hip_stream);
+
+/* Set *ok to 1 if every field word is finite, else 0 (returns TEUK_ENONFINITE then). */
+int teuk_check_finite(teuk_t *h, int *ok);
+
+/* Segment length (r* nodes per work item) of the step kernel; tuning knob, >= 1. */
+int teuk_set_tile(teuk_t *h, int segcols);
+
+/* Test hooks: the eight scaled coefficients at half nodes (which = 0,
+ * [8][n_theta][n_r-1][p]) or nodes (which = 1, [8][n_theta][n_r][p]), or the
+ * angular weights (which = 2, [2R+1][n_theta][p]).  Order of the eight:
+ * s/h b, s W, s/h K_re, s/h K_im, s Ct_re, s Ct_im, s C0_re, s C0_im with
+ * s = dt/2 at half nodes and s = dt at nodes.  set_ overwrites them (for
+ * stepping-only checks with externally supplied coefficients). */
+int teuk_get_coefficients(teuk_t *h, int which, double *out);
+int teuk_set_coefficients(teuk_t *h, int which, const double *in);
+
+/* ---- batched form: many independent instances advanced by one launch per step.
+ * Instance k has its own (s, m, a/M, grid); all share one precision.  The
+ * per-instance results are bitwise identical to the single-instance form. */
+int teuk_batch_create(int n, const int *s, const int *m, const double *a_over_M,
+                      const teuk_grid *grids, teuk_precision prec, teuk_batch_t **out);
+int teuk_batch_destroy(teuk_batch_t *b);
+int teuk_batch_set_initial(teuk_batch_t *b, int k, const double *phi_re, const double *phi_im,
+                           const double *pi_re, const double *pi_im);
+int teuk_batch_step(teuk_batch_t *b, long n);
+int teuk_batch_read_field(teuk_batch_t *b, int k, teuk_field f, double *out);
+int teuk_batch_set_stream(teuk_batch_t *b, void *hip_stream);
+int teuk_batch_size(const teuk_batch_t *b);
+double teuk_batch_dt(const teuk_batch_t *b, int k);
+int teuk_batch_set_tile(teuk_batch_t *b, int segcols);
+/* Capture the step loop in a HIP graph of `steps_per_graph` launches (0 = off). */
+int teuk_batch_use_graph(teuk_batch_t *b, int steps_per_graph);
+int teuk_use_graph(teuk_t *h, int steps_per_graph);
+
+/* Test hook for the multiword arithmetic itself: out[k] = op(a[k], b[k]) for
+ * k < n, each operand `words` doubles (1, 2 or 4), arrays [n][words].
+ * op: 0 add, 1 sub, 2 mul, 3 multiply by the double b[k][0], 4 div,
+ *     5 sqrt(a), 6 exp(a), 7 log(a), 8 sin(a), 9 cos(a) (|a| <= pi/2).
+ * _host runs the routines on the CPU, _device in a gfx950 kernel (host
+ * arrays in both cases).  Returns TEUK_OK, TEUK_EINVAL or a device error. */
+int teuk_arith_host(int words, int op, const double *a, const double *b, double *out, int n);
+int teuk_arith_device(int words, int op, const double *a, const double *b, double *out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEUK_H */

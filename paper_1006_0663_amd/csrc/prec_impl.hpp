@@ -1,0 +1,107 @@
+// Coefficient-pass driver and step launcher, templated on the number type.
+// Included once per precision by prec_f64.hip / prec_dd.hip / prec_qd.hip.
+#pragma once
+
+#include "dispatch.hpp"
+
+#pragma clang fp contract(off)
+
+namespace lwk {
+
+// Published centred-difference weights (numerator, denominator) for the first
+// and second derivative: reach 1 (second order) and reach 5 (tenth order,
+// Fornberg 1988, Table 1).
+static void stencil_weights(int reach, ThetaParams &P) {
+    static const int d1_r5_num[11] = {-1, 5, -5, 5, -5, 0, 5, -5, 5, -5, 1};
+    static const double d1_r5_den[11] = {1260, 504, 84, 21, 6, 1, 6, 21, 84, 504, 1260};
+    static const int d2_r5_num[11] = {1, -5, 5, -5, 5, -5269, 5, -5, 5, -5, 1};
+    static const double d2_r5_den[11] = {3150, 1008, 126, 21, 3, 1800, 3, 21, 126, 1008, 3150};
+    static const int d1_r1_num[3] = {-1, 0, 1};
+    static const double d1_r1_den[3] = {2, 1, 2};
+    static const int d2_r1_num[3] = {1, -2, 1};
+    static const double d2_r1_den[3] = {1, 1, 1};
+    for (int k = 0; k < 2 * reach + 1; ++k) {
+        P.c1_num[k] = reach == 5 ? d1_r5_num[k] : d1_r1_num[k];
+        P.c1_den[k] = reach == 5 ? d1_r5_den[k] : d1_r1_den[k];
+        P.c2_num[k] = reach == 5 ? d2_r5_num[k] : d2_r1_num[k];
+        P.c2_den[k] = reach == 5 ? d2_r5_den[k] : d2_r1_den[k];
+    }
+}
+
+template <class T> static void put_words(double *dst, T v) {
+    for (int w = 0; w < kMaxWords; ++w) dst[w] = w < words_of<T>::value ? mp_word(v, w) : 0.0;
+}
+
+template <class T>
+hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
+    constexpr int W = words_of<T>::value;
+    const int nr = J.nr, nth = J.nth, n = 2 * nr - 1;
+    // grid scalars, in T on the host (same routines as on the device)
+    const T rsmin = mp_from<T>(J.rstar_min);
+    const T h = mp_div_d(mp_sub(mp_from<T>(J.rstar_max), rsmin), (double)(nr - 1));
+    const T dth = mp_div_d(mp_const_pi<T>(), (double)nth);
+    const T hmin = mp_lead(mp_sub(h, dth)) < 0.0 ? h : dth;
+    const T dt = mp_mul_d(hmin, J.cfl);
+    const T hdt = mp_pow2(dt, 0.5);
+    const T ih = mp_recip(h);
+    put_words(J.hdt, hdt);
+    put_words(J.dt, dt);
+    J.dt_lead = mp_lead(dt);
+    // horizons: r+ = M + sqrt(M^2 - a^2), r- = a^2 / r+, r+ - r- = 2 sqrt(M^2 - a^2)
+    const double M = J.mass, a = J.a_over_M * J.mass;
+    RadialParams RP{nr, nr - 1, M, a, 0, 0, 0, 0};
+    T rp = mp_from<T>(0.0), dpm = mp_from<T>(0.0), A = mp_from<T>(0.0), B = mp_from<T>(0.0);
+    if (M != 0.0) {
+        const T aT = mp_from<T>(a), MT = mp_from<T>(M);
+        const T root = mp_sqrt(mp_msub(aT, aT, mp_mul(MT, MT)));     // sqrt(M^2 - a^2)
+        rp = mp_add(MT, root);
+        const T rm = mp_div(mp_mul(aT, aT), rp);
+        dpm = mp_pow2(root, 2.0);
+        A = mp_div(mp_mul_d(rp, 2.0 * M), dpm);
+        B = mp_div(mp_mul_d(rm, 2.0 * M), dpm);
+        RP.rp_d = mp_lead(rp);
+        RP.dd_d = mp_lead(dpm);
+        RP.A_d = mp_lead(A);
+        RP.B_d = mp_lead(B);
+    }
+    double *scratch = nullptr;
+    const size_t nscr = (size_t)W * (2 * (size_t)n + 2 * (size_t)nth);
+    hipError_t err = hipMalloc((void **)&scratch, nscr * sizeof(double));
+    if (err != hipSuccess) return err;
+    double *r_out = scratch, *d_out = scratch + (size_t)W * n;
+    double *cos_out = d_out + (size_t)W * n, *sin2_out = cos_out + (size_t)W * nth;
+    coef_radial_kernel<T><<<(n + 127) / 128, 128, 0, stream>>>(RP, rsmin, h, rp, dpm, A, B, r_out, d_out);
+    ThetaParams TP{};
+    TP.nth = nth;
+    TP.reach = J.reach;
+    TP.s = J.s;
+    TP.m = J.m;
+    TP.parity = (J.m % 2 != 0) ? -1 : 1;
+    stencil_weights(J.reach, TP);
+    coef_theta_kernel<T><<<(nth + 63) / 64, 64, 0, stream>>>(TP, dth, cos_out, sin2_out, J.wt);
+    PointParams PP{nr, nr - 1, nth, J.s, J.m, M, a};
+    dim3 grid((nth + 63) / 64, n);
+    coef_point_kernel<T><<<grid, 64, 0, stream>>>(PP, r_out, d_out, cos_out, sin2_out, hdt,
+                                                   mp_mul(hdt, ih), dt, mp_mul(dt, ih), J.ch, J.cf);
+    err = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(stream);
+    if (err == hipSuccess) err = e2;
+    e2 = hipFree(scratch);
+    if (err == hipSuccess) err = e2;
+    return err;
+}
+
+template <class T>
+hipError_t step_launch(int nt, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+                       hipStream_t stream) {
+    if (nitems <= 0) return hipSuccess;
+    switch (nt) {
+        case 64: lw_step_kernel<T, 64><<<nitems, 64, 0, stream>>>(insts, items, parity); break;
+        case 128: lw_step_kernel<T, 128><<<nitems, 128, 0, stream>>>(insts, items, parity); break;
+        case 256: lw_step_kernel<T, 256><<<nitems, 256, 0, stream>>>(insts, items, parity); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lwk

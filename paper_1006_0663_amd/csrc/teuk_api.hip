@@ -1,0 +1,557 @@
+// C ABI of libteuk (declared and documented in include/teuk.h).
+//
+// A single-instance handle is a batch of one: both forms build the same
+// per-instance descriptors and launch the same step kernel, so batched and
+// single-instance results are bitwise identical by construction.
+#include "teuk.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dispatch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? TEUK_ENOMEM : TEUK_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int validate(int s, int m, double a_over_M, const teuk_grid *g, int prec) {
+    (void)m;
+    if (!g) return fail(TEUK_EINVAL, "grid is NULL");
+    if (s < -2 || s > 2) return fail(TEUK_EINVAL, "spin weight s must satisfy |s| <= 2");
+    if (!(std::fabs(a_over_M) < 1.0)) return fail(TEUK_EINVAL, "|a/M| must be < 1");
+    if (g->n_theta < 5) return fail(TEUK_EINVAL, "n_theta must be >= 5 (ghost rows reflect up to 5 rows)");
+    if (g->n_theta > 256) return fail(TEUK_ENOTSUP, "n_theta > 256 is not supported by this build");
+    if (g->n_r < 3) return fail(TEUK_EINVAL, "n_r must be >= 3");
+    if ((long)g->n_r * (long)g->n_theta > (1L << 30)) return fail(TEUK_EINVAL, "grid too large");
+    if (!(g->rstar_min < g->rstar_max) || !std::isfinite(g->rstar_min) || !std::isfinite(g->rstar_max))
+        return fail(TEUK_EINVAL, "need finite rstar_min < rstar_max");
+    if (!(g->cfl > 0.0) || !std::isfinite(g->cfl)) return fail(TEUK_EINVAL, "cfl must be > 0");
+    if (g->angular_order != 10 && g->angular_order != 2)
+        return fail(TEUK_EINVAL, "angular_order must be 10 or 2");
+    if (prec != TEUK_FP64 && prec != TEUK_DD && prec != TEUK_QD)
+        return fail(TEUK_EINVAL, "precision must be 1 (FP64), 2 (double-double) or 4 (quad-double)");
+    if (g->mass == 0.0) {
+        if (a_over_M != 0.0 || !(g->rstar_min > 0.0))
+            return fail(TEUK_EINVAL, "flat-space mode (mass 0) needs a/M = 0 and rstar_min > 0");
+    } else if (g->mass != 1.0) {
+        return fail(TEUK_EINVAL, "mass must be 1.0 (or 0.0 for the flat-space test mode)");
+    }
+    return TEUK_OK;
+}
+
+struct Instance {
+    int s = 0, m = 0, words = 1, reach = 5;
+    double a_over_M = 0.0;
+    teuk_grid g{};
+    double *u[2] = {nullptr, nullptr};
+    double *ch = nullptr, *cf = nullptr, *wt = nullptr;
+    double hdt[lwk::kMaxWords] = {}, dt[lwk::kMaxWords] = {};
+    double dt_lead = 0.0;
+    int cur = 0;            // buffer holding the current fields
+    long steps = 0;
+    size_t plane() const { return (size_t)g.n_r * g.n_theta; }
+    size_t hplane() const { return (size_t)(g.n_r - 1) * g.n_theta; }
+};
+
+struct Batch {
+    int words = 1;
+    std::vector<Instance> inst;
+    int segcols = 8;
+    int nt = 64;
+    lwk::InstDev *d_inst = nullptr;
+    lwk::WorkItem *d_items = nullptr;
+    int nitems = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    int sticky = TEUK_OK;
+    int graph_steps = 0;
+    int graph_parity = -1;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+void drop_graph(Batch &b) {
+    if (b.gexec) hipGraphExecDestroy(b.gexec);
+    if (b.graph) hipGraphDestroy(b.graph);
+    b.gexec = nullptr;
+    b.graph = nullptr;
+    b.graph_parity = -1;
+}
+
+void free_batch(Batch &b) {
+    if (b.stream) hipStreamSynchronize(b.stream);
+    drop_graph(b);
+    for (auto &I : b.inst) {
+        hipFree(I.u[0]);
+        hipFree(I.u[1]);
+        hipFree(I.ch);
+        hipFree(I.cf);
+        hipFree(I.wt);
+        I.u[0] = I.u[1] = I.ch = I.cf = I.wt = nullptr;
+    }
+    hipFree(b.d_inst);
+    hipFree(b.d_items);
+    b.d_inst = nullptr;
+    b.d_items = nullptr;
+    if (b.own_stream) hipStreamDestroy(b.own_stream);
+    b.own_stream = nullptr;
+}
+
+hipError_t coef_pass(int words, lwk::CoefJob &job, hipStream_t st) {
+    switch (words) {
+        case 1: return lwk::coef_pass_f64(job, st);
+        case 2: return lwk::coef_pass_dd(job, st);
+        default: return lwk::coef_pass_qd(job, st);
+    }
+}
+
+hipError_t step_launch(const Batch &b, int parity) {
+    switch (b.words) {
+        case 1: return lwk::step_f64(b.nt, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        case 2: return lwk::step_dd(b.nt, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        default: return lwk::step_qd(b.nt, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+    }
+}
+
+// (Re)build descriptors and the work list; all instances must share `cur`.
+int build_worklist(Batch &b) {
+    int maxnth = 0;
+    for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
+    b.nt = maxnth <= 64 ? 64 : (maxnth <= 128 ? 128 : 256);
+    std::vector<lwk::InstDev> hd(b.inst.size());
+    std::vector<lwk::WorkItem> items;
+    // largest instances first
+    std::vector<int> order(b.inst.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return b.inst[x].plane() > b.inst[y].plane();
+    });
+    for (size_t k = 0; k < b.inst.size(); ++k) {
+        const Instance &I = b.inst[k];
+        lwk::InstDev &D = hd[k];
+        D.nr = I.g.n_r;
+        D.nth = I.g.n_theta;
+        D.reach = I.reach;
+        D.segcols = b.segcols;
+        const int G = b.nt / D.nth;
+        const int nseg = (D.nr + b.segcols - 1) / b.segcols;
+        D.groups = (nseg + G - 1) / G;
+        D.words = I.words;
+        D.u[0] = I.u[0];
+        D.u[1] = I.u[1];
+        D.ch = I.ch;
+        D.cf = I.cf;
+        D.wt = I.wt;
+        std::memcpy(D.hdt, I.hdt, sizeof D.hdt);
+        std::memcpy(D.dt, I.dt, sizeof D.dt);
+    }
+    for (int k : order)
+        for (int gi = 0; gi < hd[k].groups; ++gi) items.push_back({k, gi});
+    hipFree(b.d_inst);
+    hipFree(b.d_items);
+    b.d_inst = nullptr;
+    b.d_items = nullptr;
+    hipError_t e = hipMalloc((void **)&b.d_inst, hd.size() * sizeof(lwk::InstDev));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(descriptors)");
+    e = hipMalloc((void **)&b.d_items, std::max<size_t>(1, items.size()) * sizeof(lwk::WorkItem));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
+    e = hipMemcpy(b.d_inst, hd.data(), hd.size() * sizeof(lwk::InstDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(b.d_items, items.data(), items.size() * sizeof(lwk::WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work list)");
+    b.nitems = (int)items.size();
+    drop_graph(b);
+    return TEUK_OK;
+}
+
+int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, const teuk_grid *g,
+                 int prec) {
+    if (n < 1) return fail(TEUK_EINVAL, "batch size must be >= 1");
+    for (int k = 0; k < n; ++k) {
+        int rc = validate(s[k], m[k], a[k], &g[k], prec);
+        if (rc != TEUK_OK) return rc;
+    }
+    if (const char *f = std::getenv("TEUK_FAULT"))
+        if (std::strcmp(f, "alloc") == 0) return fail(TEUK_ENOMEM, "allocation failure injected by TEUK_FAULT=alloc");
+    b.words = prec;
+    hipError_t e = hipStreamCreateWithFlags(&b.own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    b.stream = b.own_stream;
+    b.inst.resize(n);
+    const int W = prec;
+    for (int k = 0; k < n; ++k) {
+        Instance &I = b.inst[k];
+        I.s = s[k];
+        I.m = m[k];
+        I.a_over_M = a[k];
+        I.g = g[k];
+        I.words = W;
+        I.reach = g[k].angular_order / 2;
+        const size_t st_bytes = 4 * (size_t)W * I.plane() * sizeof(double);
+        const size_t cf_bytes = 8 * (size_t)W * I.plane() * sizeof(double);
+        const size_t ch_bytes = 8 * (size_t)W * I.hplane() * sizeof(double);
+        const size_t wt_bytes = (size_t)(2 * I.reach + 1) * W * g[k].n_theta * sizeof(double);
+        if ((e = hipMalloc((void **)&I.u[0], st_bytes)) != hipSuccess ||
+            (e = hipMalloc((void **)&I.u[1], st_bytes)) != hipSuccess ||
+            (e = hipMalloc((void **)&I.cf, cf_bytes)) != hipSuccess ||
+            (e = hipMalloc((void **)&I.ch, ch_bytes)) != hipSuccess ||
+            (e = hipMalloc((void **)&I.wt, wt_bytes)) != hipSuccess)
+            return hip_fail(e, "hipMalloc(instance arrays)");
+        if ((e = hipMemsetAsync(I.u[0], 0, st_bytes, b.stream)) != hipSuccess ||
+            (e = hipMemsetAsync(I.u[1], 0, st_bytes, b.stream)) != hipSuccess)
+            return hip_fail(e, "hipMemset(state)");
+        lwk::CoefJob J{};
+        J.s = I.s;
+        J.m = I.m;
+        J.nr = g[k].n_r;
+        J.nth = g[k].n_theta;
+        J.reach = I.reach;
+        J.a_over_M = a[k];
+        J.mass = g[k].mass;
+        J.rstar_min = g[k].rstar_min;
+        J.rstar_max = g[k].rstar_max;
+        J.cfl = g[k].cfl;
+        J.ch = I.ch;
+        J.cf = I.cf;
+        J.wt = I.wt;
+        if ((e = coef_pass(W, J, b.stream)) != hipSuccess) return hip_fail(e, "coefficient pass");
+        std::memcpy(I.hdt, J.hdt, sizeof I.hdt);
+        std::memcpy(I.dt, J.dt, sizeof I.dt);
+        I.dt_lead = J.dt_lead;
+    }
+    if ((e = hipStreamSynchronize(b.stream)) != hipSuccess) return hip_fail(e, "coefficient pass (sync)");
+    return build_worklist(b);
+}
+
+int check_ok(Batch &b) {
+    if (b.sticky != TEUK_OK) return fail(b.sticky, "handle is in a failed state after an earlier device error");
+    return TEUK_OK;
+}
+
+// host interchange [j][i][w]  <->  device planar [w][i][j]
+int upload_field(Batch &b, Instance &I, int comp, const double *src, int buf) {
+    const int W = I.words, nr = I.g.n_r, nth = I.g.n_theta;
+    std::vector<double> tmp((size_t)W * I.plane());
+    for (int j = 0; j < nth; ++j)
+        for (int i = 0; i < nr; ++i)
+            for (int w = 0; w < W; ++w) {
+                double v = src[((size_t)j * nr + i) * W + w];
+                if (i == 0 || i == nr - 1) v = 0.0;
+                tmp[(size_t)w * I.plane() + (size_t)i * nth + j] = v;
+            }
+    hipError_t e = hipMemcpyAsync(I.u[buf] + (size_t)comp * W * I.plane(), tmp.data(),
+                                  tmp.size() * sizeof(double), hipMemcpyHostToDevice, b.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) return hip_fail(e, "upload");
+    return TEUK_OK;
+}
+
+int download_planes(Batch &b, const double *dsrc, int nplanes_w, int nr, int nth, int W, double *out) {
+    // dsrc holds W planes of nr x nth (theta fastest); out is [nth][nr][W]
+    std::vector<double> tmp((size_t)W * nr * nth);
+    hipError_t e = hipStreamSynchronize(b.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tmp.data(), dsrc, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, b.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "download");
+    }
+    (void)nplanes_w;
+    const size_t plane = (size_t)nr * nth;
+    for (int j = 0; j < nth; ++j)
+        for (int i = 0; i < nr; ++i)
+            for (int w = 0; w < W; ++w)
+                out[((size_t)j * nr + i) * W + w] = tmp[(size_t)w * plane + (size_t)i * nth + j];
+    return TEUK_OK;
+}
+
+int set_initial(Batch &b, int k, const double *pr, const double *pim, const double *qr, const double *qim) {
+    if (int rc = check_ok(b)) return rc;
+    if (k < 0 || k >= (int)b.inst.size()) return fail(TEUK_EINVAL, "instance index out of range");
+    if (!pr || !pim || !qr || !qim) return fail(TEUK_EINVAL, "field pointer is NULL");
+    Instance &I = b.inst[k];
+    // all instances of a batch step together: keep them on the same buffer
+    int buf = I.cur;
+    const double *src[4] = {pr, pim, qr, qim};
+    for (int c = 0; c < 4; ++c)
+        if (int rc = upload_field(b, I, c, src[c], buf)) return rc;
+    I.steps = 0;
+    return TEUK_OK;
+}
+
+int do_steps(Batch &b, long n) {
+    if (int rc = check_ok(b)) return rc;
+    if (n < 0) return fail(TEUK_EINVAL, "step count must be >= 0");
+    int cur = b.inst[0].cur;
+    long left = n;
+    hipError_t e = hipSuccess;
+    if (b.graph_steps > 0 && left >= b.graph_steps) {
+        if (!b.gexec || b.graph_parity != cur) {
+            drop_graph(b);
+            e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int q = 0; q < b.graph_steps && e == hipSuccess; ++q) e = step_launch(b, (cur + q) & 1);
+                hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
+                if (e == hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b.gexec, b.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                b.sticky = TEUK_EDEVICE;
+                drop_graph(b);
+                return hip_fail(e, "graph capture");
+            }
+            b.graph_parity = cur;
+        }
+        while (left >= b.graph_steps && e == hipSuccess) {
+            e = hipGraphLaunch(b.gexec, b.stream);
+            left -= b.graph_steps;
+            cur = (cur + b.graph_steps) & 1;
+        }
+    }
+    for (; left > 0 && e == hipSuccess; --left) {
+        e = step_launch(b, cur);
+        cur ^= 1;
+    }
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "step launch");
+    }
+    for (auto &I : b.inst) {
+        I.cur = cur;
+        I.steps += n;
+    }
+    return TEUK_OK;
+}
+
+int read_field(Batch &b, int k, int f, double *out) {
+    if (int rc = check_ok(b)) return rc;
+    if (k < 0 || k >= (int)b.inst.size()) return fail(TEUK_EINVAL, "instance index out of range");
+    if (f < 0 || f > 3 || !out) return fail(TEUK_EINVAL, "bad field or NULL output");
+    Instance &I = b.inst[k];
+    return download_planes(b, I.u[I.cur] + (size_t)f * I.words * I.plane(), 1, I.g.n_r, I.g.n_theta, I.words, out);
+}
+
+int set_stream(Batch &b, void *st) {
+    if (b.stream) hipStreamSynchronize(b.stream);
+    b.stream = st ? (hipStream_t)st : b.own_stream;
+    drop_graph(b);
+    return TEUK_OK;
+}
+
+}  // namespace
+
+struct teuk {
+    Batch b;
+};
+struct teuk_batch {
+    Batch b;
+};
+
+extern "C" {
+
+int teuk_abi_version(void) { return TEUK_ABI_VERSION; }
+const char *teuk_build_info(void) { return "libteuk gfx950 fp64/dd/qd lax-wendroff"; }
+const char *teuk_last_error(void) { return g_err.c_str(); }
+
+int teuk_validate(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec) {
+    return validate(s, m, a_over_M, grid, (int)prec);
+}
+
+int teuk_create(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec, teuk_t **out) {
+    if (!out) return fail(TEUK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(s, m, a_over_M, grid, (int)prec);
+    if (rc != TEUK_OK) return rc;
+    teuk_t *h = new (std::nothrow) teuk_t;
+    if (!h) return fail(TEUK_ENOMEM, "host allocation");
+    rc = create_batch(h->b, 1, &s, &m, &a_over_M, grid, (int)prec);
+    if (rc != TEUK_OK) {
+        free_batch(h->b);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return TEUK_OK;
+}
+
+int teuk_destroy(teuk_t *h) {
+    if (!h) return TEUK_OK;
+    free_batch(h->b);
+    delete h;
+    return TEUK_OK;
+}
+
+int teuk_set_initial(teuk_t *h, const double *a, const double *b, const double *c, const double *d) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_initial(h->b, 0, a, b, c, d);
+}
+int teuk_step(teuk_t *h, long n) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return do_steps(h->b, n);
+}
+int teuk_read_field(teuk_t *h, teuk_field f, double *out) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return read_field(h->b, 0, (int)f, out);
+}
+double teuk_dt(const teuk_t *h) { return h ? h->b.inst[0].dt_lead : 0.0; }
+long teuk_steps_done(const teuk_t *h) { return h ? h->b.inst[0].steps : -1; }
+int teuk_words(const teuk_t *h) { return h ? h->b.words : 0; }
+int teuk_set_step_index(teuk_t *h, long n) {
+    if (!h || n < 0) return fail(TEUK_EINVAL, "bad handle or step index");
+    h->b.inst[0].steps = n;
+    return TEUK_OK;
+}
+int teuk_set_stream(teuk_t *h, void *st) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_stream(h->b, st);
+}
+int teuk_use_graph(teuk_t *h, int k) {
+    if (!h || k < 0) return fail(TEUK_EINVAL, "bad handle or graph length");
+    drop_graph(h->b);
+    h->b.graph_steps = k;
+    return TEUK_OK;
+}
+int teuk_set_tile(teuk_t *h, int segcols) {
+    if (!h || segcols < 1) return fail(TEUK_EINVAL, "bad handle or tile");
+    if (int rc = check_ok(h->b)) return rc;
+    hipStreamSynchronize(h->b.stream);
+    h->b.segcols = segcols;
+    return build_worklist(h->b);
+}
+
+int teuk_check_finite(teuk_t *h, int *ok) {
+    if (!h || !ok) return fail(TEUK_EINVAL, "NULL argument");
+    Instance &I = h->b.inst[0];
+    std::vector<double> tmp((size_t)I.words * I.plane());
+    *ok = 1;
+    for (int f = 0; f < 4; ++f) {
+        int rc = read_field(h->b, 0, f, tmp.data());
+        if (rc) return rc;
+        for (double v : tmp)
+            if (!std::isfinite(v)) *ok = 0;
+    }
+    return *ok ? TEUK_OK : fail(TEUK_ENONFINITE, "a field holds Inf or NaN");
+}
+
+int teuk_get_coefficients(teuk_t *h, int which, double *out) {
+    if (!h || !out || which < 0 || which > 2) return fail(TEUK_EINVAL, "bad arguments");
+    Batch &b = h->b;
+    Instance &I = b.inst[0];
+    const int W = I.words, nth = I.g.n_theta;
+    if (which == 2) {
+        const int taps = 2 * I.reach + 1;
+        for (int k = 0; k < taps; ++k) {
+            // one "row" of nth entries per tap: reuse the plane download with nr = 1
+            int rc = download_planes(b, I.wt + (size_t)k * W * nth, 1, 1, nth, W, out + (size_t)k * nth * W);
+            if (rc) return rc;
+        }
+        return TEUK_OK;
+    }
+    const int nr = which == 0 ? I.g.n_r - 1 : I.g.n_r;
+    const double *src = which == 0 ? I.ch : I.cf;
+    const size_t plane = (size_t)nr * nth;
+    for (int c = 0; c < 8; ++c) {
+        int rc = download_planes(b, src + (size_t)c * W * plane, 1, nr, nth, W, out + (size_t)c * plane * W);
+        if (rc) return rc;
+    }
+    return TEUK_OK;
+}
+
+int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
+    if (!h || !in || which < 0 || which > 1) return fail(TEUK_EINVAL, "bad arguments");
+    Batch &b = h->b;
+    if (int rc = check_ok(b)) return rc;
+    Instance &I = b.inst[0];
+    const int W = I.words, nth = I.g.n_theta;
+    const int nr = which == 0 ? I.g.n_r - 1 : I.g.n_r;
+    double *dst = which == 0 ? I.ch : I.cf;
+    const size_t plane = (size_t)nr * nth;
+    std::vector<double> tmp((size_t)W * plane);
+    for (int c = 0; c < 8; ++c) {
+        for (int j = 0; j < nth; ++j)
+            for (int i = 0; i < nr; ++i)
+                for (int w = 0; w < W; ++w)
+                    tmp[(size_t)w * plane + (size_t)i * nth + j] = in[(size_t)c * plane * W + ((size_t)j * nr + i) * W + w];
+        hipError_t e = hipMemcpyAsync(dst + (size_t)c * W * plane, tmp.data(), tmp.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, b.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+        if (e != hipSuccess) return hip_fail(e, "set coefficients");
+    }
+    return TEUK_OK;
+}
+
+// ---------------------------------------------------------------- batched
+int teuk_batch_create(int n, const int *s, const int *m, const double *a, const teuk_grid *grids,
+                      teuk_precision prec, teuk_batch_t **out) {
+    if (!out || !s || !m || !a || !grids) return fail(TEUK_EINVAL, "NULL argument");
+    *out = nullptr;
+    teuk_batch_t *b = new (std::nothrow) teuk_batch_t;
+    if (!b) return fail(TEUK_ENOMEM, "host allocation");
+    int rc = create_batch(b->b, n, s, m, a, grids, (int)prec);
+    if (rc != TEUK_OK) {
+        free_batch(b->b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return TEUK_OK;
+}
+int teuk_batch_destroy(teuk_batch_t *b) {
+    if (!b) return TEUK_OK;
+    free_batch(b->b);
+    delete b;
+    return TEUK_OK;
+}
+int teuk_batch_set_initial(teuk_batch_t *b, int k, const double *p, const double *q, const double *r,
+                           const double *t) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_initial(b->b, k, p, q, r, t);
+}
+int teuk_batch_step(teuk_batch_t *b, long n) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return do_steps(b->b, n);
+}
+int teuk_batch_read_field(teuk_batch_t *b, int k, teuk_field f, double *out) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return read_field(b->b, k, (int)f, out);
+}
+int teuk_batch_set_stream(teuk_batch_t *b, void *st) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_stream(b->b, st);
+}
+int teuk_batch_size(const teuk_batch_t *b) { return b ? (int)b->b.inst.size() : 0; }
+double teuk_batch_dt(const teuk_batch_t *b, int k) {
+    return (b && k >= 0 && k < (int)b->b.inst.size()) ? b->b.inst[k].dt_lead : 0.0;
+}
+int teuk_batch_set_tile(teuk_batch_t *b, int segcols) {
+    if (!b || segcols < 1) return fail(TEUK_EINVAL, "bad handle or tile");
+    if (int rc = check_ok(b->b)) return rc;
+    hipStreamSynchronize(b->b.stream);
+    b->b.segcols = segcols;
+    return build_worklist(b->b);
+}
+int teuk_batch_use_graph(teuk_batch_t *b, int k) {
+    if (!b || k < 0) return fail(TEUK_EINVAL, "bad handle or graph length");
+    drop_graph(b->b);
+    b->b.graph_steps = k;
+    return TEUK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+"""GPU parity of the hot path against the oracle (small grids: several r*
+segments plus a ragged tail, every precision), and the bitwise invariants of
+the library (batched == single, checkpoint restart, graph replay, round trip)."""
+import sys
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_1006_0663_amd import inputs, teuk as T
+from oracle import engine, problem
+from parity_util import oracle_run, rel_linf, to_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {1: 1e-12, 2: 1e-28, 4: 1e-60}
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _grid(w):
+    return T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
+
+
+def _run_gpu(w, fields, nsteps, tile=None):
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), w.words)
+    if tile:
+        h.set_tile(tile)
+    h.set_initial(*fields)
+    h.step(nsteps)
+    out = h.fields()
+    h.close()
+    return out
+
+
+SMALL = [
+    # (label, workload)  -- pulses moved inside the short domains
+    ("fp64-m2", inputs.C1.with_(n_r=61, n_theta=16, rstar_min=60.0, rstar_max=150.0, words=1)),
+    ("fp64-m1-a0.9", inputs.C1.with_(n_r=45, n_theta=12, rstar_min=70.0, rstar_max=140.0, m=1, a_over_M=0.9, words=1)),
+    ("fp64-order2", inputs.C1.with_(n_r=37, n_theta=9, rstar_min=70.0, rstar_max=140.0, angular_order=2, words=1)),
+    ("dd-m2", inputs.C1.with_(n_r=61, n_theta=16, rstar_min=60.0, rstar_max=150.0, words=2)),
+    ("dd-m3-a0.99", inputs.C4.with_(n_r=45, n_theta=12, rstar_min=60.0, rstar_max=150.0, m=3, words=2)),
+    ("qd-m2-a0.99", inputs.C4.with_(n_r=45, n_theta=12, rstar_min=60.0, rstar_max=150.0, words=4)),
+    ("qd-m0-a0.3", inputs.C1.with_(n_r=37, n_theta=8, rstar_min=70.0, rstar_max=140.0, m=0, a_over_M=0.3, words=4)),
+]
+
+
+@pytest.mark.parametrize("label,w", SMALL, ids=[x[0] for x in SMALL])
+def test_small_grid_parity(label, w):
+    nsteps = 24
+    fields = inputs.initial_fields(w)
+    _note("parity %s: %dx%d words=%d steps=%d" % (label, w.n_r, w.n_theta, w.words, nsteps))
+    got = _run_gpu(w, fields, nsteps, tile=8)
+    ref = oracle_run(w, fields, nsteps)
+    err = rel_linf(got, ref)
+    _note("  rel Linf = %.3e (tolerance %.0e)" % (err, TOL[w.words]))
+    assert err <= TOL[w.words]
+
+
+@pytest.mark.parametrize("words", [1, 2, 4])
+def test_coefficients_match_oracle(words):
+    """Coefficient pass against the oracle's 450-bit Kerr factors, including
+    nodes next to the horizon (r* = -200) and far out (r* = 800)."""
+    w = inputs.C2.with_(n_r=21, n_theta=8, words=words, a_over_M=0.9, m=3)
+    _note("coefficients words=%d" % words)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), words)
+    got = [h.coefficients(0), h.coefficients(1)]
+    h.close()
+    tab = problem.build_tables(to_problem(w))
+    with mp.workprec(450):
+        scal = {0: (tab["dt"] / 2, tab["dt"] / 2 / tab["h"]), 1: (tab["dt"], tab["dt"] / tab["h"])}
+        for which, key in ((0, "half"), (1, "full")):
+            s, si = scal[which]
+            for c in range(8):
+                worst, mx = mp.mpf(0), mp.mpf(0)
+                for j in range(w.n_theta):
+                    for i in range(len(tab[key][j])):
+                        b, W, K, Ct, C0 = tab[key][j][i]
+                        ref = [si * b, s * W, si * K.real, si * K.imag, s * Ct.real, s * Ct.imag,
+                               s * C0.real, s * C0.imag][c]
+                        v = sum(mp.mpf(x) for x in got[which][c, j, i])
+                        worst = max(worst, abs(v - ref))
+                        mx = max(mx, abs(ref))
+                rel = worst / mx if mx else worst
+                assert rel <= TOL[words] / 100, (which, c, float(rel))
+
+
+def test_batched_equals_single_bitwise():
+    ws = [inputs.C1.with_(n_r=40 + 7 * k, n_theta=nth, rstar_min=60.0, rstar_max=150.0, m=k % 3,
+                          a_over_M=0.2 * k, words=2, seed=k)
+          for k, nth in enumerate((8, 16, 12, 32))]
+    _note("batched vs single, %d instances" % len(ws))
+    b = T.TeukBatch([(w.s, w.m, w.a_over_M, _grid(w)) for w in ws], 2)
+    b.set_tile(6)
+    fields = [inputs.initial_fields(w) for w in ws]
+    for k, f in enumerate(fields):
+        b.set_initial(k, *f)
+    b.step(15)
+    for k, w in enumerate(ws):
+        single = _run_gpu(w, fields[k], 15, tile=6)
+        for f in range(4):
+            assert np.array_equal(b.read_field(k, f), single[f]), (k, f)
+    b.close()
+
+
+def test_checkpoint_restart_and_graph_are_bitwise():
+    w = inputs.C1.with_(n_r=50, n_theta=16, rstar_min=60.0, rstar_max=150.0, words=4)
+    fields = inputs.initial_fields(w)
+    _note("checkpoint/graph qd 50x16")
+    full = _run_gpu(w, fields, 10)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 4)
+    h.set_initial(*fields)
+    h.step(5)
+    mid = h.fields()
+    assert h.steps_done == 5
+    h.set_initial(*mid)
+    h.set_step_index(5)
+    h.step(5)
+    assert h.steps_done == 10
+    for f in range(4):
+        assert np.array_equal(h.read_field(f), full[f])
+    h.set_initial(*fields)
+    h.use_graph(4)
+    h.step(10)                    # 2 graph replays + 2 plain launches
+    for f in range(4):
+        assert np.array_equal(h.read_field(f), full[f])
+    h.close()
+
+
+def test_round_trip_and_edges():
+    # smallest legal grid, zero steps, boundary columns forced to zero
+    w = inputs.C1.with_(n_r=3, n_theta=5, rstar_min=0.0, rstar_max=10.0, words=2)
+    rng = np.random.default_rng(0)
+    f = [rng.standard_normal((5, 3, 2)) for _ in range(4)]
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 2)
+    h.set_initial(*f)
+    h.step(0)
+    for c in range(4):
+        exp = f[c].copy()
+        exp[:, 0] = exp[:, -1] = 0
+        assert np.array_equal(h.read_field(c), exp)
+    h.step(3)
+    ref = oracle_run(w, [h_ for h_ in [np.where(np.arange(3)[None, :, None] % 2 == 1, x, 0) for x in f]], 3)
+    got = h.fields()
+    assert rel_linf(got, ref) <= TOL[2]
+    assert h.check_finite()
+    h.close()
+
+
+@pytest.mark.parametrize("words", [1, 2, 4])
+def test_device_arithmetic_matches_host(words):
+    rng = np.random.default_rng(words)
+    a = rng.standard_normal((257, words)) * np.array([1, 2 ** -60, 2 ** -120, 2 ** -180][:words])
+    b = rng.standard_normal((257, words)) * np.array([1, 2 ** -60, 2 ** -120, 2 ** -180][:words])
+    for op in (0, 1, 2, 3, 4):
+        assert np.array_equal(T.arith(words, op, a, b, device=True), T.arith(words, op, a, b)), op
