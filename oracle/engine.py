@@ -47,13 +47,37 @@ def _load():
 
 
 # ---------------------------------------------------------------- conversions
+def round_scaled(x, bits: int) -> int:
+    """Nearest integer to x * 2^bits, ties away from zero, computed exactly from
+    the number's integer mantissa and exponent (x an mpf, Fraction, int or float).
+    (mpmath's own routines would work at the context precision, 53 bits by
+    default, and silently drop the low bits.)"""
+    if isinstance(x, int):
+        return x << bits
+    if isinstance(x, float):
+        x = Fraction(x)
+    if isinstance(x, Fraction):
+        n = abs(x.numerator) << bits
+        q, r = divmod(n, x.denominator)
+        q += 1 if 2 * r >= x.denominator else 0
+        return -q if x.numerator < 0 else q
+    # read the stored (sign, mantissa, exponent) directly: constructing or
+    # scaling an mpf would round it to the ambient context precision
+    sign, man, exp, bc = (x if isinstance(x, mp.mpf) else mp.mpf(x))._mpf_
+    if man == 0 and (exp != 0 or bc != 0):
+        raise ValueError("non-finite value")
+    shift = exp + bits
+    if shift >= 0:
+        q = man << shift
+    else:
+        q, r = divmod(man, 1 << -shift)
+        q += 1 if 2 * r >= (1 << -shift) else 0
+    return -q if sign else q
+
+
 def mp_to_fixed(x) -> int:
     """Nearest integer to x * 2^FRAC (x an mp number, Fraction or int)."""
-    if isinstance(x, Fraction):
-        n = x.numerator << FRAC
-        q, r = divmod(n, x.denominator)
-        return q + (1 if 2 * r >= x.denominator else 0)
-    return int(mp.nint(mp.ldexp(x, FRAC)))
+    return round_scaled(x, FRAC)
 
 
 def words_to_fixed(words) -> int:

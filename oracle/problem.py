@@ -139,8 +139,10 @@ def to_fractions(tables, bits: int = 120):
     Used by the exact-arithmetic brute force: the rounded tables define a
     scheme whose exact evolution is computable in Fractions.
     """
+    from .engine import round_scaled
+
     def q(x):
-        return Fraction(int(mp.nint(mp.ldexp(x, bits))), 1 << bits)
+        return Fraction(round_scaled(x, bits), 1 << bits)
 
     def qc(z):
         if isinstance(z, mp.mpc):

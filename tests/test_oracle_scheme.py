@@ -221,3 +221,36 @@ def test_radial_boundaries_stay_zero():
     for c in range(4):
         for j in range(p.n_theta):
             assert out[c * n + j * nr] == 0 and out[c * n + j * nr + nr - 1] == 0
+
+
+def test_engine_matches_450bit_scheme_with_full_precision_tables():
+    """The engine fed the 450-bit mpmath tables directly (not dyadic-rounded
+    ones) agrees with the Python scheme run at 450 bits: pins the conversion
+    of wide mpmath numbers into fixed point."""
+    p = problem.Problem(s=-2, m=1, a_over_M=0.7, n_r=10, n_theta=7, rstar_min=-5.0, rstar_max=40.0)
+    tab = problem.build_tables(p)
+    rng = np.random.default_rng(12)
+    f = [rng.standard_normal((p.n_theta, p.n_r)) for _ in range(4)]
+    for x in f:
+        x[:, 0] = x[:, -1] = 0
+    out = engine.run_problem(p, f, 2, tables=tab)
+    n = p.n_r * p.n_theta
+    with mp.workprec(450):
+        TP = scheme.as_pairs(tab)
+        phi = [[(mp.mpf(f[0][j, i]), mp.mpf(f[1][j, i])) for i in range(p.n_r)] for j in range(p.n_theta)]
+        pi = [[(mp.mpf(f[2][j, i]), mp.mpf(f[3][j, i])) for i in range(p.n_r)] for j in range(p.n_theta)]
+        phi, pi = scheme.evolve(phi, pi, TP, 2, mp.mpf(1) / 2)
+        worst = max(abs(mp.mpf(out[c * n + j * p.n_r + i]) / mp.mpf(2) ** FRAC - arr[j][i][c % 2])
+                    for c, arr in enumerate((phi, phi, pi, pi)) for j in range(p.n_theta) for i in range(p.n_r))
+        assert worst < mp.mpf(2) ** -360, float(worst)
+
+
+def test_round_scaled_is_exact_for_wide_numbers():
+    with mp.workprec(450):
+        x = -mp.pi / 7
+        negx = -x
+    assert engine.round_scaled(x, 400) == -engine.round_scaled(negx, 400)
+    with mp.workprec(900):
+        ref = int(mp.nint(mp.ldexp(x, 400)))
+    assert engine.round_scaled(x, 400) == ref
+    assert engine.round_scaled(Fraction(-3, 8), 2) == -2 and engine.round_scaled(Fraction(5, 8), 2) == 3
