@@ -73,11 +73,9 @@ struct RadialParams {
 // Delta = x (x + r_plus - r_minus) keeps full relative precision at the
 // horizon end of the grid.  Outputs r and Delta (T, planar, n_full + n_half).
 template <class T>
-__global__ void coef_radial_kernel(RadialParams P, T rsmin, T h, T rp, T dpm, T A, T B,
-                                   double *r_out, double *delta_out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+MPA void coef_radial_one(const RadialParams &P, int t, T rsmin, T h, T rp, T dpm, T A, T B,
+                         double *r_out, double *delta_out) {
     const int n = P.n_full + P.n_half;
-    if (t >= n) return;
     const double idx = t < P.n_full ? (double)t : (double)(t - P.n_full) + 0.5;
     const T rs = mp_madd(mp_from<T>(idx), h, rsmin);          // idx has <= 15 significant bits: exact in T
     T r, delta;
@@ -116,6 +114,13 @@ __global__ void coef_radial_kernel(RadialParams P, T rsmin, T h, T rp, T dpm, T 
     st(delta_out, (size_t)n, (size_t)t, delta);
 }
 
+template <class T>
+__global__ void coef_radial_kernel(RadialParams P, T rsmin, T h, T rp, T dpm, T A, T B,
+                                   double *r_out, double *delta_out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < P.n_full + P.n_half) coef_radial_one<T>(P, t, rsmin, h, rp, dpm, A, B, r_out, delta_out);
+}
+
 struct ThetaParams {
     int nth, reach, s, m, parity;
     int c1_num[2 * kMaxReach + 1], c2_num[2 * kMaxReach + 1];
@@ -124,9 +129,7 @@ struct ThetaParams {
 
 // Per theta row: cos, sin^2 (for the point kernel) and the folded angular weights.
 template <class T>
-__global__ void coef_theta_kernel(ThetaParams P, T dth, double *cos_out, double *sin2_out, double *wt) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P.nth) return;
+MPA void coef_theta_one(const ThetaParams &P, int j, T dth, double *cos_out, double *sin2_out, double *wt) {
     const T th = mp_mul(mp_from<T>((double)j + 0.5), dth);   // (j + 1/2) dth
     const T x = mp_sub(th, mp_pow2(mp_const_pi<T>(), 0.5));  // theta - pi/2 in (-pi/2, pi/2)
     T sx, cx_;
@@ -153,6 +156,12 @@ __global__ void coef_theta_kernel(ThetaParams P, T dth, double *cos_out, double 
     st(sin2_out, (size_t)P.nth, (size_t)j, sin2);
 }
 
+template <class T>
+__global__ void coef_theta_kernel(ThetaParams P, T dth, double *cos_out, double *sin2_out, double *wt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < P.nth) coef_theta_one<T>(P, j, dth, cos_out, sin2_out, wt);
+}
+
 struct PointParams {
     int n_full, n_half, nth, s, m;
     double mass, a;
@@ -167,13 +176,10 @@ struct PointParams {
 //   b d_r* b = a^2 Delta sin^2 (varpi Delta' - 4 r Delta) q^2 / 2,
 //   K = b d_r* b - b Ct - Cs,   Delta' = 2 (r - M).
 template <class T>
-__global__ void coef_point_kernel(PointParams P, const double *r_in, const double *delta_in,
-                                  const double *cos_in, const double *sin2_in, T s_half, T si_half,
-                                  T s_full, T si_full, double *ch, double *cf) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = blockIdx.y;
+MPA void coef_point_one(const PointParams &P, int t, int j, const double *r_in, const double *delta_in,
+                        const double *cos_in, const double *sin2_in, T s_half, T si_half,
+                        T s_full, T si_full, double *ch, double *cf) {
     const int n = P.n_full + P.n_half;
-    if (j >= P.nth || t >= n) return;
     const T r = ld<T>(r_in, (size_t)n, (size_t)t);
     const T delta = ld<T>(delta_in, (size_t)n, (size_t)t);
     const T cost = ld<T>(cos_in, (size_t)P.nth, (size_t)j);
@@ -220,6 +226,16 @@ __global__ void coef_point_kernel(PointParams P, const double *r_in, const doubl
     for (int c = 0; c < 8; ++c) st(out + (size_t)c * Wd * plane, plane, idx, vals[c]);
 }
 
+template <class T>
+__global__ void coef_point_kernel(PointParams P, const double *r_in, const double *delta_in,
+                                  const double *cos_in, const double *sin2_in, T s_half, T si_half,
+                                  T s_full, T si_full, double *ch, double *cf) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
+    if (j < P.nth && t < P.n_full + P.n_half)
+        coef_point_one<T>(P, t, j, r_in, delta_in, cos_in, sin2_in, s_half, si_half, s_full, si_full, ch, cf);
+}
+
 // ------------------------------------------------------------------ step kernel
 template <class T> struct Pt {
     cx<T> phi, pi;
@@ -231,7 +247,7 @@ template <class T> struct Pt {
 // with bar = neighbour average, d = neighbour difference, coefficients
 // pre-scaled by s (= dt/2 or dt) and 1/dr*; for (lw1) base = bar.
 template <class T>
-__device__ __forceinline__ Pt<T> lw_stage(const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d,
+MPA Pt<T> lw_stage(const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d,
                                           const cx<T> &lbar, const T *c, const T &s) {
     Pt<T> o;
     o.phi = c_rmadd(s, bar.pi, c_rmsub(c[0], d.phi, base.phi));
@@ -244,7 +260,7 @@ __device__ __forceinline__ Pt<T> lw_stage(const Pt<T> &base, const Pt<T> &bar, c
 }
 
 template <class T>
-__device__ __forceinline__ Pt<T> ld_pt(const double *u, size_t plane, size_t idx) {
+MPA Pt<T> ld_pt(const double *u, size_t plane, size_t idx) {
     constexpr int W = words_of<T>::value;
     Pt<T> p;
     p.phi.re = ld<T>(u + 0 * W * plane, plane, idx);
@@ -254,7 +270,7 @@ __device__ __forceinline__ Pt<T> ld_pt(const double *u, size_t plane, size_t idx
     return p;
 }
 template <class T>
-__device__ __forceinline__ void st_pt(double *u, size_t plane, size_t idx, const Pt<T> &p) {
+MPA void st_pt(double *u, size_t plane, size_t idx, const Pt<T> &p) {
     constexpr int W = words_of<T>::value;
     st(u + 0 * W * plane, plane, idx, p.phi.re);
     st(u + 1 * W * plane, plane, idx, p.phi.im);
@@ -262,10 +278,10 @@ __device__ __forceinline__ void st_pt(double *u, size_t plane, size_t idx, const
     st(u + 3 * W * plane, plane, idx, p.pi.im);
 }
 
-template <class T> __device__ __forceinline__ Pt<T> pt_avg(const Pt<T> &a, const Pt<T> &b) {
+template <class T> MPA Pt<T> pt_avg(const Pt<T> &a, const Pt<T> &b) {
     return {c_pow2(c_add(a.phi, b.phi), 0.5), c_pow2(c_add(a.pi, b.pi), 0.5)};
 }
-template <class T> __device__ __forceinline__ Pt<T> pt_diff(const Pt<T> &a, const Pt<T> &b) {
+template <class T> MPA Pt<T> pt_diff(const Pt<T> &a, const Pt<T> &b) {
     return {c_sub(b.phi, a.phi), c_sub(b.pi, a.pi)};
 }
 

@@ -32,57 +32,74 @@ template <class T> static void put_words(double *dst, T v) {
     for (int w = 0; w < kMaxWords; ++w) dst[w] = w < words_of<T>::value ? mp_word(v, w) : 0.0;
 }
 
-template <class T>
-hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
-    constexpr int W = words_of<T>::value;
-    const int nr = J.nr, nth = J.nth, n = 2 * nr - 1;
-    // grid scalars, in T on the host (same routines as on the device)
-    const T rsmin = mp_from<T>(J.rstar_min);
-    const T h = mp_div_d(mp_sub(mp_from<T>(J.rstar_max), rsmin), (double)(nr - 1));
-    const T dth = mp_div_d(mp_const_pi<T>(), (double)nth);
-    const T hmin = mp_lead(mp_sub(h, dth)) < 0.0 ? h : dth;
-    const T dt = mp_mul_d(hmin, J.cfl);
-    const T hdt = mp_pow2(dt, 0.5);
-    const T ih = mp_recip(h);
-    put_words(J.hdt, hdt);
-    put_words(J.dt, dt);
-    J.dt_lead = mp_lead(dt);
+// Grid scalars and horizon quantities of one instance, in T (computed on the
+// host with the same routines the kernels use).
+template <class T> struct CoefSetup {
+    T rsmin, h, dth, dt, hdt, ih;
+    T rp, dpm, A, B;
+    RadialParams RP;
+    ThetaParams TP;
+    PointParams PP;
+};
+
+template <class T> CoefSetup<T> coef_setup(CoefJob &J) {
+    CoefSetup<T> S{};
+    const int nr = J.nr, nth = J.nth;
+    S.rsmin = mp_from<T>(J.rstar_min);
+    S.h = mp_div_d(mp_sub(mp_from<T>(J.rstar_max), S.rsmin), (double)(nr - 1));
+    S.dth = mp_div_d(mp_const_pi<T>(), (double)nth);
+    const T hmin = mp_lead(mp_sub(S.h, S.dth)) < 0.0 ? S.h : S.dth;
+    S.dt = mp_mul_d(hmin, J.cfl);
+    S.hdt = mp_pow2(S.dt, 0.5);
+    S.ih = mp_recip(S.h);
+    put_words(J.hdt, S.hdt);
+    put_words(J.dt, S.dt);
+    J.dt_lead = mp_lead(S.dt);
     // horizons: r+ = M + sqrt(M^2 - a^2), r- = a^2 / r+, r+ - r- = 2 sqrt(M^2 - a^2)
     const double M = J.mass, a = J.a_over_M * J.mass;
-    RadialParams RP{nr, nr - 1, M, a, 0, 0, 0, 0};
-    T rp = mp_from<T>(0.0), dpm = mp_from<T>(0.0), A = mp_from<T>(0.0), B = mp_from<T>(0.0);
+    S.RP = RadialParams{nr, nr - 1, M, a, 0, 0, 0, 0};
+    S.rp = S.dpm = S.A = S.B = mp_from<T>(0.0);
     if (M != 0.0) {
         const T aT = mp_from<T>(a), MT = mp_from<T>(M);
         const T root = mp_sqrt(mp_msub(aT, aT, mp_mul(MT, MT)));     // sqrt(M^2 - a^2)
-        rp = mp_add(MT, root);
-        const T rm = mp_div(mp_mul(aT, aT), rp);
-        dpm = mp_pow2(root, 2.0);
-        A = mp_div(mp_mul_d(rp, 2.0 * M), dpm);
-        B = mp_div(mp_mul_d(rm, 2.0 * M), dpm);
-        RP.rp_d = mp_lead(rp);
-        RP.dd_d = mp_lead(dpm);
-        RP.A_d = mp_lead(A);
-        RP.B_d = mp_lead(B);
+        S.rp = mp_add(MT, root);
+        const T rm = mp_div(mp_mul(aT, aT), S.rp);
+        S.dpm = mp_pow2(root, 2.0);
+        S.A = mp_div(mp_mul_d(S.rp, 2.0 * M), S.dpm);
+        S.B = mp_div(mp_mul_d(rm, 2.0 * M), S.dpm);
+        S.RP.rp_d = mp_lead(S.rp);
+        S.RP.dd_d = mp_lead(S.dpm);
+        S.RP.A_d = mp_lead(S.A);
+        S.RP.B_d = mp_lead(S.B);
     }
+    S.TP = ThetaParams{};
+    S.TP.nth = nth;
+    S.TP.reach = J.reach;
+    S.TP.s = J.s;
+    S.TP.m = J.m;
+    S.TP.parity = (J.m % 2 != 0) ? -1 : 1;
+    stencil_weights(J.reach, S.TP);
+    S.PP = PointParams{nr, nr - 1, nth, J.s, J.m, M, a};
+    return S;
+}
+
+template <class T>
+hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
+    constexpr int W = words_of<T>::value;
+    const int nth = J.nth, n = 2 * J.nr - 1;
+    CoefSetup<T> S = coef_setup<T>(J);
     double *scratch = nullptr;
     const size_t nscr = (size_t)W * (2 * (size_t)n + 2 * (size_t)nth);
     hipError_t err = hipMalloc((void **)&scratch, nscr * sizeof(double));
     if (err != hipSuccess) return err;
     double *r_out = scratch, *d_out = scratch + (size_t)W * n;
     double *cos_out = d_out + (size_t)W * n, *sin2_out = cos_out + (size_t)W * nth;
-    coef_radial_kernel<T><<<(n + 127) / 128, 128, 0, stream>>>(RP, rsmin, h, rp, dpm, A, B, r_out, d_out);
-    ThetaParams TP{};
-    TP.nth = nth;
-    TP.reach = J.reach;
-    TP.s = J.s;
-    TP.m = J.m;
-    TP.parity = (J.m % 2 != 0) ? -1 : 1;
-    stencil_weights(J.reach, TP);
-    coef_theta_kernel<T><<<(nth + 63) / 64, 64, 0, stream>>>(TP, dth, cos_out, sin2_out, J.wt);
-    PointParams PP{nr, nr - 1, nth, J.s, J.m, M, a};
+    coef_radial_kernel<T><<<(n + 127) / 128, 128, 0, stream>>>(S.RP, S.rsmin, S.h, S.rp, S.dpm, S.A, S.B,
+                                                               r_out, d_out);
+    coef_theta_kernel<T><<<(nth + 63) / 64, 64, 0, stream>>>(S.TP, S.dth, cos_out, sin2_out, J.wt);
     dim3 grid((nth + 63) / 64, n);
-    coef_point_kernel<T><<<grid, 64, 0, stream>>>(PP, r_out, d_out, cos_out, sin2_out, hdt,
-                                                   mp_mul(hdt, ih), dt, mp_mul(dt, ih), J.ch, J.cf);
+    coef_point_kernel<T><<<grid, 64, 0, stream>>>(S.PP, r_out, d_out, cos_out, sin2_out, S.hdt,
+                                                   mp_mul(S.hdt, S.ih), S.dt, mp_mul(S.dt, S.ih), J.ch, J.cf);
     err = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(stream);
     if (err == hipSuccess) err = e2;

@@ -72,6 +72,7 @@ def test_coefficients_match_oracle(words):
     tab = problem.build_tables(to_problem(w))
     with mp.workprec(450):
         scal = {0: (tab["dt"] / 2, tab["dt"] / 2 / tab["h"]), 1: (tab["dt"], tab["dt"] / tab["h"])}
+        report = []
         for which, key in ((0, "half"), (1, "full")):
             s, si = scal[which]
             for c in range(8):
@@ -83,9 +84,13 @@ def test_coefficients_match_oracle(words):
                                s * C0.real, s * C0.imag][c]
                         v = sum(mp.mpf(x) for x in got[which][c, j, i])
                         worst = max(worst, abs(v - ref))
-                        mx = max(mx, abs(ref))
+                        # K can cancel to zero: scale its error by the cancelling terms
+                        mx = max(mx, abs(ref), abs(si * b * Ct) if c in (2, 3) else 0)
                 rel = worst / mx if mx else worst
-                assert rel <= TOL[words] / 100, (which, c, float(rel))
+                report.append((which, c, float(rel)))
+        _note("  coefficient rel errors: %s" % report)
+        for which, c, rel in report:
+            assert rel <= TOL[words] / 100, (which, c, rel)
 
 
 def test_batched_equals_single_bitwise():
