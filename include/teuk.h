@@ -25,8 +25,10 @@
  * Host field arrays ("interchange layout") are row-major [n_theta][n_r][p]
  * doubles: theta row j, then r* node i (fastest over nodes), then the p words
  * of one real (p = 1, 2 or 4, leading word first).  A p-word real is the exact
- * sum of its words; inputs are taken as given and results are non-overlapping
- * expansions.  The device layout is private to the library.
+ * sum of its words.  Inputs are renormalised on upload into non-overlapping
+ * expansions (exactly for 2 words; for 4 words exactly whenever the input
+ * already is one, otherwise rounded in the last word); results are
+ * non-overlapping expansions.  The device layout is private to the library.
  *
  * Ownership: the library owns every handle and all device memory.  Host
  * buffers belong to the caller and are only accessed during the call.

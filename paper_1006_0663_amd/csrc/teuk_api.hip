@@ -249,12 +249,19 @@ int upload_field(Batch &b, Instance &I, int comp, const double *src, int buf) {
     const int W = I.words, nr = I.g.n_r, nth = I.g.n_theta;
     std::vector<double> tmp((size_t)W * I.plane());
     for (int j = 0; j < nth; ++j)
-        for (int i = 0; i < nr; ++i)
-            for (int w = 0; w < W; ++w) {
-                double v = src[((size_t)j * nr + i) * W + w];
-                if (i == 0 || i == nr - 1) v = 0.0;
-                tmp[(size_t)w * I.plane() + (size_t)i * nth + j] = v;
+        for (int i = 0; i < nr; ++i) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            if (i != 0 && i != nr - 1)
+                for (int w = 0; w < W; ++w) v[w] = src[((size_t)j * nr + i) * W + w];
+            // renormalise to a non-overlapping expansion (the kernels assume one)
+            if (W == 2) {
+                lwk::two_sum(v[0], v[1], v[0], v[1]);
+            } else if (W == 4) {
+                const lwk::qd q = lwk::qd_renorm(v[0], v[1], v[2], v[3], 0.0);
+                v[0] = q.x0; v[1] = q.x1; v[2] = q.x2; v[3] = q.x3;
             }
+            for (int w = 0; w < W; ++w) tmp[(size_t)w * I.plane() + (size_t)i * nth + j] = v[w];
+        }
     hipError_t e = hipMemcpyAsync(I.u[buf] + (size_t)comp * W * I.plane(), tmp.data(),
                                   tmp.size() * sizeof(double), hipMemcpyHostToDevice, b.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b.stream);

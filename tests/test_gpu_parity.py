@@ -144,9 +144,11 @@ def test_round_trip_and_edges():
     h.set_initial(*f)
     h.step(0)
     for c in range(4):
-        exp = f[c].copy()
-        exp[:, 0] = exp[:, -1] = 0
-        assert np.array_equal(h.read_field(c), exp)
+        got = h.read_field(c)
+        assert np.all(got[:, [0, 2]] == 0)
+        # interior values are renormalised exactly: same sum, |lo| <= ulp(hi)/2
+        assert np.array_equal(got[:, 1, 0] + got[:, 1, 1], f[c][:, 1, 0] + f[c][:, 1, 1])
+        assert np.all(got[:, 1, 0] == (f[c][:, 1, 0] + f[c][:, 1, 1]))
     h.step(3)
     ref = oracle_run(w, [h_ for h_ in [np.where(np.arange(3)[None, :, None] % 2 == 1, x, 0) for x in f]], 3)
     got = h.fields()
