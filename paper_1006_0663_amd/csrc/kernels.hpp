@@ -23,6 +23,7 @@
 // left edge, so segments are independent and one launch advances a step.
 #pragma once
 
+#include "mpdot.hpp"
 #include "mpfunc.hpp"
 
 #pragma clang fp contract(off)
@@ -245,17 +246,54 @@ template <class T> struct Pt {
 //   out_Phi = base_Phi - B dPhi + s Pibar
 //   out_Pi  = base_Pi  + B dPi - K dPhi + W Lbar + C0 Phibar - Ct Pibar
 // with bar = neighbour average, d = neighbour difference, coefficients
-// pre-scaled by s (= dt/2 or dt) and 1/dr*; for (lw1) base = bar.
+// pre-scaled by s (= dt/2 or dt) and 1/dr*; for (lw1) base = bar.  Each of
+// the four real outputs is one fused dot product (see mpdot.hpp).
 template <class T>
-MPA Pt<T> lw_stage(const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d,
-                                          const cx<T> &lbar, const T *c, const T &s) {
+MPA Pt<T> lw_stage(const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d, const cx<T> &lbar, const T *c,
+                   const T &s) {
+    const T nB = mp_neg(c[0]), nKr = mp_neg(c[2]), nKi = mp_neg(c[3]);
+    const T nCr = mp_neg(c[4]), nCi = mp_neg(c[5]), nDi = mp_neg(c[7]);
     Pt<T> o;
-    o.phi = c_rmadd(s, bar.pi, c_rmsub(c[0], d.phi, base.phi));
-    cx<T> acc = c_rmadd(c[0], d.pi, base.pi);
-    acc = c_msub(c[2], c[3], d.phi, acc);
-    acc = c_rmadd(c[1], lbar, acc);
-    acc = c_madd(c[6], c[7], bar.phi, acc);
-    o.pi = c_msub(c[4], c[5], bar.pi, acc);
+    {
+        Acc<T> a;
+        a.value(base.phi.re);
+        a.prod(nB, d.phi.re);
+        a.prod(s, bar.pi.re);
+        o.phi.re = a.result();
+    }
+    {
+        Acc<T> a;
+        a.value(base.phi.im);
+        a.prod(nB, d.phi.im);
+        a.prod(s, bar.pi.im);
+        o.phi.im = a.result();
+    }
+    {
+        Acc<T> a;                                   // Re: + B dPi - K dPhi + W L + C0 Phi - Ct Pi
+        a.value(base.pi.re);
+        a.prod(c[0], d.pi.re);
+        a.prod(nKr, d.phi.re);
+        a.prod(c[3], d.phi.im);
+        a.prod(c[1], lbar.re);
+        a.prod(c[6], bar.phi.re);
+        a.prod(nDi, bar.phi.im);
+        a.prod(nCr, bar.pi.re);
+        a.prod(c[5], bar.pi.im);
+        o.pi.re = a.result();
+    }
+    {
+        Acc<T> a;                                   // Im
+        a.value(base.pi.im);
+        a.prod(c[0], d.pi.im);
+        a.prod(nKr, d.phi.im);
+        a.prod(nKi, d.phi.re);
+        a.prod(c[1], lbar.im);
+        a.prod(c[6], bar.phi.im);
+        a.prod(c[7], bar.phi.re);
+        a.prod(nCr, bar.pi.im);
+        a.prod(nCi, bar.pi.re);
+        o.pi.im = a.result();
+    }
     return o;
 }
 
@@ -278,12 +316,14 @@ MPA void st_pt(double *u, size_t plane, size_t idx, const Pt<T> &p) {
     st(u + 3 * W * plane, plane, idx, p.pi.im);
 }
 
-template <class T> MPA Pt<T> pt_avg(const Pt<T> &a, const Pt<T> &b) {
-    return {c_pow2(c_add(a.phi, b.phi), 0.5), c_pow2(c_add(a.pi, b.pi), 0.5)};
+template <class T> MPA cx<T> c_avg(const cx<T> &a, const cx<T> &b) {
+    return {mp_pow2(mp_add_fast(a.re, b.re), 0.5), mp_pow2(mp_add_fast(a.im, b.im), 0.5)};
 }
-template <class T> MPA Pt<T> pt_diff(const Pt<T> &a, const Pt<T> &b) {
-    return {c_sub(b.phi, a.phi), c_sub(b.pi, a.pi)};
+template <class T> MPA cx<T> c_diff(const cx<T> &a, const cx<T> &b) {     // b - a
+    return {mp_add_fast(b.re, mp_neg(a.re)), mp_add_fast(b.im, mp_neg(a.im))};
 }
+template <class T> MPA Pt<T> pt_avg(const Pt<T> &a, const Pt<T> &b) { return {c_avg(a.phi, b.phi), c_avg(a.pi, b.pi)}; }
+template <class T> MPA Pt<T> pt_diff(const Pt<T> &a, const Pt<T> &b) { return {c_diff(a.phi, b.phi), c_diff(a.pi, b.pi)}; }
 
 // Angular operator of the value v held by lane j of a group, via the LDS
 // buffer buf.  Callers alternate strictly between two buffers, so the single
@@ -291,18 +331,30 @@ template <class T> MPA Pt<T> pt_diff(const Pt<T> &a, const Pt<T> &b) {
 // lane's reads of the same buffer two exchanges earlier.
 template <class T>
 __device__ __forceinline__ cx<T> theta_apply(cx<T> v, cx<T> *buf, int j, int nth, int reach,
-                                             const T *w, bool active) {
+                                             const double *__restrict__ wt, bool active) {
+    constexpr int W = words_of<T>::value;
     if (active) buf[j] = v;
     __syncthreads();
-    cx<T> acc = {mp_from<T>(0.0), mp_from<T>(0.0)};
-#pragma unroll
-    for (int k = -kMaxReach; k <= kMaxReach; ++k) {
-        if (k < -reach || k > reach) continue;
+    Acc<T> re, im;
+    auto tap = [&](int k) {
         int q = j + k;
         q = q < 0 ? -1 - q : (q >= nth ? 2 * nth - 1 - q : q);
-        acc = c_rmadd(w[k + kMaxReach], buf[q], acc);
+        const cx<T> x = buf[q];
+        const T w = ld<T>(wt + (size_t)(k + reach) * W * nth, (size_t)nth, (size_t)j);
+        re.prod(w, x.re);
+        im.prod(w, x.im);
+    };
+    if constexpr (W == 1) {
+        // double: unrolled, all loads issued together
+#pragma unroll
+        for (int k = -kMaxReach; k <= kMaxReach; ++k)
+            if (k >= -reach && k <= reach) tap(k);
+    } else {
+        // multiword: a rolled loop keeps only one tap's operands live
+#pragma unroll 1
+        for (int k = -reach; k <= reach; ++k) tap(k);
     }
-    return acc;
+    return {re.result(), im.result()};
 }
 
 template <class T, int NT>
@@ -324,15 +376,8 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     const size_t plane = (size_t)nr * nth, hplane = (size_t)(nr - 1) * nth;
     const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
 
-    // angular weights of this row, kept in registers
-    T wk[2 * kMaxReach + 1];
-#pragma unroll
-    for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
-        const int kk = k - kMaxReach;
-        wk[k] = (lane_on && kk >= -R && kk <= R)
-                    ? ld<T>(I.wt + (size_t)(kk + R) * W * nth, (size_t)nth, (size_t)j)
-                    : mp_from<T>(0.0);
-    }
+    // angular weights of this row (wt + tap * W * nth); rows of idle lanes read row 0
+    const double *wrow = I.wt;
     cx<T> *buf0 = &lds[0][lane_on ? g * nth : 0], *buf1 = &lds[1][lane_on ? g * nth : 0];
 
     // zero radial boundary nodes owned by this segment
@@ -352,7 +397,7 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         const int col = a + t;
         const bool col_on = seg_on && col <= e;
         u_cur = col_on ? ld_pt<T>(uin, plane, (size_t)col * nth + j) : zero;
-        l_cur = theta_apply(u_cur.phi, buf0, j, nth, R, wk, lane_on);
+        l_cur = theta_apply<T>(u_cur.phi, buf0, lane_on ? j : 0, nth, R, wrow, lane_on);
         // (lw1) at half node (col-1)+1/2
         const bool h_on = col_on && t >= 1;
         T c[8];
@@ -363,10 +408,10 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         {
             const Pt<T> bar = pt_avg(u_prev, u_cur);
             const Pt<T> d = pt_diff(u_prev, u_cur);
-            const cx<T> lbar = c_pow2(c_add(l_prev, l_cur), 0.5);
+            const cx<T> lbar = c_avg(l_prev, l_cur);
             uh_cur = lw_stage(bar, bar, d, lbar, c, hdt);
         }
-        lh_cur = theta_apply(uh_cur.phi, buf1, j, nth, R, wk, lane_on);
+        lh_cur = theta_apply<T>(uh_cur.phi, buf1, lane_on ? j : 0, nth, R, wrow, lane_on);
         if (h_on && t >= 2) {
             // (lw2) at node col-1
             const int i = col - 1;
@@ -375,7 +420,7 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
                 c[q] = ld<T>(I.cf + (size_t)q * W * plane, plane, (size_t)i * nth + j);
             const Pt<T> barh = pt_avg(uh_prev, uh_cur);
             const Pt<T> dh = pt_diff(uh_prev, uh_cur);
-            const cx<T> lbarh = c_pow2(c_add(lh_prev, lh_cur), 0.5);
+            const cx<T> lbarh = c_avg(lh_prev, lh_cur);
             const Pt<T> un = lw_stage(u_prev, barh, dh, lbarh, c, dt);
             st_pt(uout, plane, (size_t)i * nth + j, un);
         }

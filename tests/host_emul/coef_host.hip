@@ -44,13 +44,15 @@ static void step_host(int nr, int nth, int R, const double *ch, const double *cf
     const size_t plane = (size_t)nr * nth, hplane = (size_t)(nr - 1) * nth;
     const T hdt = from_words<T>(hdtw), dt = from_words<T>(dtw);
     auto theta = [&](const std::vector<cx<T>> &col, int j) {
-        cx<T> acc = {mp_from<T>(0.0), mp_from<T>(0.0)};
+        Acc<T> re, im;
         for (int k = -R; k <= R; ++k) {
             int q = j + k;
             q = q < 0 ? -1 - q : (q >= nth ? 2 * nth - 1 - q : q);
-            acc = c_rmadd(ld<T>(wt + (size_t)(k + R) * W * nth, (size_t)nth, (size_t)j), col[q], acc);
+            const T w = ld<T>(wt + (size_t)(k + R) * W * nth, (size_t)nth, (size_t)j);
+            re.prod(w, col[q].re);
+            im.prod(w, col[q].im);
         }
-        return acc;
+        return cx<T>{re.result(), im.result()};
     };
     std::vector<Pt<T>> u((size_t)nr * nth), uh((size_t)(nr - 1) * nth);
     std::vector<cx<T>> L((size_t)nr * nth), Lh((size_t)(nr - 1) * nth), col(nth);
@@ -67,7 +69,7 @@ static void step_host(int nr, int nth, int R, const double *ch, const double *cf
             const Pt<T> &a = u[(size_t)i * nth + j], &b = u[(size_t)(i + 1) * nth + j];
             const Pt<T> bar = pt_avg(a, b);
             uh[(size_t)i * nth + j] = lw_stage(bar, bar, pt_diff(a, b),
-                                               c_pow2(c_add(L[(size_t)i * nth + j], L[(size_t)(i + 1) * nth + j]), 0.5), c, hdt);
+                                               c_avg(L[(size_t)i * nth + j], L[(size_t)(i + 1) * nth + j]), c, hdt);
         }
     for (int i = 0; i + 1 < nr; ++i) {
         for (int j = 0; j < nth; ++j) col[j] = uh[(size_t)i * nth + j].phi;
@@ -84,7 +86,7 @@ static void step_host(int nr, int nth, int R, const double *ch, const double *cf
             for (int q = 0; q < 8; ++q) c[q] = ld<T>(cf + (size_t)q * W * plane, plane, (size_t)i * nth + j);
             const Pt<T> &a = uh[(size_t)(i - 1) * nth + j], &b = uh[(size_t)i * nth + j];
             const Pt<T> un = lw_stage(u[(size_t)i * nth + j], pt_avg(a, b), pt_diff(a, b),
-                                      c_pow2(c_add(Lh[(size_t)(i - 1) * nth + j], Lh[(size_t)i * nth + j]), 0.5), c, dt);
+                                      c_avg(Lh[(size_t)(i - 1) * nth + j], Lh[(size_t)i * nth + j]), c, dt);
             st_pt(uout, plane, (size_t)i * nth + j, un);
         }
 }
