@@ -119,8 +119,11 @@ int teuk_set_stream(teuk_t *h, void *hip_stream);
 /* Set *ok to 1 if every field word is finite, else 0 (returns TEUK_ENONFINITE then). */
 int teuk_check_finite(teuk_t *h, int *ok);
 
-/* Segment length (r* nodes per work item) of the step kernel; tuning knob, >= 1. */
+/* Launch shape of the step kernel (tuning knobs, results are unaffected):
+ * segcols = r* nodes per work item (>= 1); block = threads per workgroup
+ * (64, 128 or 256, at least n_theta; 0 = smallest that fits). */
 int teuk_set_tile(teuk_t *h, int segcols);
+int teuk_set_launch(teuk_t *h, int segcols, int block);
 
 /* Test hooks: the eight scaled coefficients at half nodes (which = 0,
  * [8][n_theta][n_r-1][p]) or nodes (which = 1, [8][n_theta][n_r][p]), or the
@@ -145,6 +148,7 @@ int teuk_batch_set_stream(teuk_batch_t *b, void *hip_stream);
 int teuk_batch_size(const teuk_batch_t *b);
 double teuk_batch_dt(const teuk_batch_t *b, int k);
 int teuk_batch_set_tile(teuk_batch_t *b, int segcols);
+int teuk_batch_set_launch(teuk_batch_t *b, int segcols, int block);
 /* Capture the step loop in a HIP graph of `steps_per_graph` launches (0 = off). */
 int teuk_batch_use_graph(teuk_batch_t *b, int steps_per_graph);
 int teuk_use_graph(teuk_t *h, int steps_per_graph);

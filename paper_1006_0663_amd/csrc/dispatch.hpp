@@ -13,6 +13,8 @@ struct CoefJob {
     int s, m, nr, nth, reach;
     double a_over_M, mass, rstar_min, rstar_max, cfl;
     double *ch, *cf, *wt;            // device outputs (planar, see kernels.hpp)
+    int onfly;                       // FP64: write radial rows + theta factors instead of planes
+    double *rf, *rh, *trig;          // device outputs when onfly
     double hdt[kMaxWords], dt[kMaxWords];   // scalars written by the pass (words of T)
     double dt_lead;
 };
@@ -21,6 +23,10 @@ struct CoefJob {
 hipError_t coef_pass_f64(CoefJob &job, hipStream_t stream);
 hipError_t coef_pass_dd(CoefJob &job, hipStream_t stream);
 hipError_t coef_pass_qd(CoefJob &job, hipStream_t stream);
+
+// FP64 test hook: the coefficient planes rebuilt from radial rows and theta factors.
+hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, const double *trig, double *cf,
+                       double *ch, hipStream_t stream);
 
 // One step of every work item: block size nt in {64, 128, 256}.
 hipError_t step_f64(int nt, const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream);

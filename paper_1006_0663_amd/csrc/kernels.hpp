@@ -38,10 +38,119 @@ struct InstDev {
     int nr, nth, reach, segcols;
     int groups;                 // number of segment groups (blocks) of this instance
     int words;
+    int onfly;                  // FP64 only: evaluate coefficients per point from rh/rf/trig
     double *u[2];
     const double *ch, *cf, *wt;
+    const double *rh, *rf;      // radial rows (kRadRow doubles) at half nodes / nodes
+    const double *trig;         // [2][nth]: cos(theta_j), sin^2(theta_j)
     double hdt[kMaxWords], dt[kMaxWords];
 };
+
+// ------------------------------------------------------------------ FP64 per-point coefficients
+// For FP64 the step kernel can rebuild the eight scaled coefficients of a
+// point from one row of radial factors (wave-uniform along the r* sweep) and
+// cos, sin^2 of its theta row, instead of reading 16 stored doubles per
+// update.  With Sigma^2 = varpi^2 - a^2 Delta sin^2, q = 1/Sigma^2, s = dt/2
+// (half nodes) or dt (nodes), i = 1/dr* and
+//   T1 = 2s'(r Delta - M(r^2-a^2)), T2 = 4Mamr, T3 = 2s'a Delta,
+//   T4 = Delta(6 Delta/r^2 + 3(s'+1)Delta'/r), T5 = 6am Delta/r + 4ams'(r-M),
+//   T6 = Delta(6 varpi/r + 2r) + varpi s' Delta', T7 = 2am varpi,
+//   T8 = a^2 Delta (varpi Delta' - 4 r Delta)/2          (s' = spin weight)
+// the coefficients are s i b, s W, s i K, s Ct, s C0 with b = varpi sqrt(q),
+// W = Delta q, Ct = q (T1 + i(T2 + T3 cos)), C0 = q (T4 + i T5),
+// Cs = q (T6 + i T7), b d_r*b = sin^2 q^2 T8, K = b d_r*b - b Ct - Cs.
+constexpr int kRadRow = 16;
+enum {
+    kVp2, kA2D, kVp, kSD, kSIVp, kST1, kST2, kST3, kST4, kST5, kSIT1, kSIT2, kSIT3, kSIT6, kSIT7, kSIT8
+};
+
+// 1/sqrt(x), x > 0: correctly rounded float seed, two Newton steps in double
+// (same basic operations on host and device, so both give the same bits)
+MPA double rsqrt_nr(double x) {
+    double y = (double)(1.0f / sqrtf((float)x));
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
+}
+
+MPA void coef_fp64_point(const double *rr, double cs, double s2, double *c) {
+    const double X = fma(-rr[kA2D], s2, rr[kVp2]);
+    const double rq = rsqrt_nr(X);
+    const double q = rq * rq;
+    const double b = rr[kVp] * rq;
+    c[0] = rr[kSIVp] * rq;
+    c[1] = rr[kSD] * q;
+    c[2] = q * fma(s2 * q, rr[kSIT8], -fma(b, rr[kSIT1], rr[kSIT6]));
+    c[3] = -q * fma(b, fma(rr[kSIT3], cs, rr[kSIT2]), rr[kSIT7]);
+    c[4] = q * rr[kST1];
+    c[5] = q * fma(rr[kST3], cs, rr[kST2]);
+    c[6] = q * rr[kST4];
+    c[7] = q * rr[kST5];
+}
+
+// radial row of location t (nodes first, then half nodes) from r and Delta
+MPA void coef_fp64_radial_row(int s_, int m_, double M, double a, double r, double delta, double sg,
+                              double sgi, double *row) {
+    const double s = s_, m = m_;
+    const double a2 = a * a, r2 = r * r, vp = r2 + a2, dd = 2.0 * (r - M), ir = 1.0 / r;
+    const double T1 = 2.0 * s * fma(r, delta, -M * (r2 - a2));
+    const double T2 = 4.0 * M * a * m * r;
+    const double T3 = 2.0 * s * a * delta;
+    const double T4 = delta * fma(3.0 * (s + 1.0) * dd, ir, 6.0 * delta * ir * ir);
+    const double T5 = fma(6.0 * a * m * delta, ir, 4.0 * a * m * s * (r - M));
+    const double T6 = fma(delta, fma(6.0 * vp, ir, 2.0 * r), vp * s * dd);
+    const double T7 = 2.0 * a * m * vp;
+    const double T8 = 0.5 * a2 * delta * fma(vp, dd, -4.0 * r * delta);
+    row[kVp2] = vp * vp;
+    row[kA2D] = a2 * delta;
+    row[kVp] = vp;
+    row[kSD] = sg * delta;
+    row[kSIVp] = sgi * vp;
+    row[kST1] = sg * T1;
+    row[kST2] = sg * T2;
+    row[kST3] = sg * T3;
+    row[kST4] = sg * T4;
+    row[kST5] = sg * T5;
+    row[kSIT1] = sgi * T1;
+    row[kSIT2] = sgi * T2;
+    row[kSIT3] = sgi * T3;
+    row[kSIT6] = sgi * T6;
+    row[kSIT7] = sgi * T7;
+    row[kSIT8] = sgi * T8;
+}
+
+struct Fp64RowParams {
+    int n_full, n_half, s, m;
+    double mass, a, s_half, si_half, s_full, si_full;
+};
+
+static __global__ void coef_fp64_rows_kernel(Fp64RowParams P, const double *r_in, const double *delta_in,
+                                      double *rf, double *rh) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = P.n_full + P.n_half;
+    if (t >= n) return;
+    const bool half = t >= P.n_full;
+    double *row = half ? rh + (size_t)(t - P.n_full) * kRadRow : rf + (size_t)t * kRadRow;
+    coef_fp64_radial_row(P.s, P.m, P.mass, P.a, r_in[t], delta_in[t], half ? P.s_half : P.s_full,
+                         half ? P.si_half : P.si_full, row);
+}
+
+// the planes of the test hook, from the same per-point routine the kernel uses
+static __global__ void coef_fp64_planes_kernel(int nr, int nth, const double *rf, const double *rh, const double *trig,
+                                        double *cf, double *ch) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y;
+    if (j >= nth || t >= 2 * nr - 1) return;
+    const bool half = t >= nr;
+    const int i = half ? t - nr : t;
+    const int ni = half ? nr - 1 : nr;
+    double c[8];
+    coef_fp64_point((half ? rh : rf) + (size_t)i * kRadRow, trig[j], trig[nth + j], c);
+    double *out = half ? ch : cf;
+    const size_t plane = (size_t)ni * nth;
+    for (int k = 0; k < 8; ++k) out[(size_t)k * plane + (size_t)i * nth + j] = c[k];
+}
 
 struct WorkItem {
     int inst;
@@ -357,6 +466,26 @@ __device__ __forceinline__ cx<T> theta_apply(cx<T> v, cx<T> *buf, int j, int nth
     return {re.result(), im.result()};
 }
 
+// eight coefficients of node/half node i at row j: from the stored planes, or
+// (FP64 with onfly) rebuilt from the radial row and the row's cos, sin^2
+template <class T>
+__device__ __forceinline__ void load_coef(const InstDev &I, const double *planes, const double *rows,
+                                          size_t plane, bool on, int i, int j, double cs, double s2, T *c) {
+    constexpr int W = words_of<T>::value;
+    if constexpr (W == 1) {
+        if (I.onfly) {
+            double cc[8];
+            coef_fp64_point(rows + (size_t)(on ? i : 0) * kRadRow, cs, s2, cc);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = on ? cc[q] : 0.0;
+            return;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        c[q] = on ? ld<T>(planes + (size_t)q * W * plane, plane, (size_t)i * I.nth + j) : mp_from<T>(0.0);
+}
+
 template <class T, int NT>
 __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__ insts,
                                                      const WorkItem *__restrict__ items, int parity) {
@@ -386,6 +515,12 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         if (c0 == 0) st_pt(uout, plane, (size_t)j, z);
         if (c1 == nr) st_pt(uout, plane, (size_t)(nr - 1) * nth + j, z);
     }
+    // theta factors of this row for the FP64 per-point coefficients
+    double cs_j = 0.0, s2_j = 0.0;
+    if (words_of<T>::value == 1 && I.onfly && lane_on) {
+        cs_j = I.trig[j];
+        s2_j = I.trig[nth + j];
+    }
     const int a = max(c0, 1) - 1;          // first node read
     const int e = min(c1, nr - 1);         // interior outputs are nodes a+1 .. e-1
     const Pt<T> zero = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
@@ -401,10 +536,7 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         // (lw1) at half node (col-1)+1/2
         const bool h_on = col_on && t >= 1;
         T c[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            c[q] = h_on ? ld<T>(I.ch + (size_t)q * W * hplane, hplane, (size_t)(col - 1) * nth + j)
-                        : mp_from<T>(0.0);
+        load_coef<T>(I, I.ch, I.rh, hplane, h_on, col - 1, j, cs_j, s2_j, c);
         {
             const Pt<T> bar = pt_avg(u_prev, u_cur);
             const Pt<T> d = pt_diff(u_prev, u_cur);
@@ -415,9 +547,7 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         if (h_on && t >= 2) {
             // (lw2) at node col-1
             const int i = col - 1;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                c[q] = ld<T>(I.cf + (size_t)q * W * plane, plane, (size_t)i * nth + j);
+            load_coef<T>(I, I.cf, I.rf, plane, true, i, j, cs_j, s2_j, c);
             const Pt<T> barh = pt_avg(uh_prev, uh_cur);
             const Pt<T> dh = pt_diff(uh_prev, uh_cur);
             const cx<T> lbarh = c_avg(lh_prev, lh_cur);

@@ -7,4 +7,10 @@ hipError_t step_f64(int nt, const InstDev *insts, const WorkItem *items, int nit
                    hipStream_t stream) {
     return step_launch<double>(nt, insts, items, nitems, parity, stream);
 }
+hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, const double *trig, double *cf,
+                       double *ch, hipStream_t stream) {
+    dim3 grid((nth + 63) / 64, 2 * nr - 1);
+    coef_fp64_planes_kernel<<<grid, 64, 0, stream>>>(nr, nth, rf, rh, trig, cf, ch);
+    return hipGetLastError();
+}
 }  // namespace lwk

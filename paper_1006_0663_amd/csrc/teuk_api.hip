@@ -61,6 +61,8 @@ struct Instance {
     teuk_grid g{};
     double *u[2] = {nullptr, nullptr};
     double *ch = nullptr, *cf = nullptr, *wt = nullptr;
+    int onfly = 0;                                   // FP64: per-point coefficients from rows
+    double *rf = nullptr, *rh = nullptr, *trig = nullptr;
     double hdt[lwk::kMaxWords] = {}, dt[lwk::kMaxWords] = {};
     double dt_lead = 0.0;
     int cur = 0;            // buffer holding the current fields
@@ -74,6 +76,7 @@ struct Batch {
     std::vector<Instance> inst;
     int segcols = 8;
     int nt = 64;
+    int nt_req = 0;          // requested block size (0 = smallest that fits)
     lwk::InstDev *d_inst = nullptr;
     lwk::WorkItem *d_items = nullptr;
     int nitems = 0;
@@ -103,7 +106,10 @@ void free_batch(Batch &b) {
         hipFree(I.ch);
         hipFree(I.cf);
         hipFree(I.wt);
-        I.u[0] = I.u[1] = I.ch = I.cf = I.wt = nullptr;
+        hipFree(I.rf);
+        hipFree(I.rh);
+        hipFree(I.trig);
+        I.u[0] = I.u[1] = I.ch = I.cf = I.wt = I.rf = I.rh = I.trig = nullptr;
     }
     hipFree(b.d_inst);
     hipFree(b.d_items);
@@ -134,6 +140,7 @@ int build_worklist(Batch &b) {
     int maxnth = 0;
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     b.nt = maxnth <= 64 ? 64 : (maxnth <= 128 ? 128 : 256);
+    if (b.nt_req > b.nt) b.nt = b.nt_req;
     std::vector<lwk::InstDev> hd(b.inst.size());
     std::vector<lwk::WorkItem> items;
     // largest instances first
@@ -158,6 +165,10 @@ int build_worklist(Batch &b) {
         D.ch = I.ch;
         D.cf = I.cf;
         D.wt = I.wt;
+        D.onfly = I.onfly;
+        D.rf = I.rf;
+        D.rh = I.rh;
+        D.trig = I.trig;
         std::memcpy(D.hdt, I.hdt, sizeof D.hdt);
         std::memcpy(D.dt, I.dt, sizeof D.dt);
     }
@@ -207,12 +218,20 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
         const size_t cf_bytes = 8 * (size_t)W * I.plane() * sizeof(double);
         const size_t ch_bytes = 8 * (size_t)W * I.hplane() * sizeof(double);
         const size_t wt_bytes = (size_t)(2 * I.reach + 1) * W * g[k].n_theta * sizeof(double);
+        I.onfly = (W == 1);
         if ((e = hipMalloc((void **)&I.u[0], st_bytes)) != hipSuccess ||
             (e = hipMalloc((void **)&I.u[1], st_bytes)) != hipSuccess ||
-            (e = hipMalloc((void **)&I.cf, cf_bytes)) != hipSuccess ||
-            (e = hipMalloc((void **)&I.ch, ch_bytes)) != hipSuccess ||
             (e = hipMalloc((void **)&I.wt, wt_bytes)) != hipSuccess)
             return hip_fail(e, "hipMalloc(instance arrays)");
+        if (I.onfly) {
+            if ((e = hipMalloc((void **)&I.rf, (size_t)lwk::kRadRow * g[k].n_r * sizeof(double))) != hipSuccess ||
+                (e = hipMalloc((void **)&I.rh, (size_t)lwk::kRadRow * (g[k].n_r - 1) * sizeof(double))) != hipSuccess ||
+                (e = hipMalloc((void **)&I.trig, 2 * (size_t)g[k].n_theta * sizeof(double))) != hipSuccess)
+                return hip_fail(e, "hipMalloc(coefficient rows)");
+        } else if ((e = hipMalloc((void **)&I.cf, cf_bytes)) != hipSuccess ||
+                   (e = hipMalloc((void **)&I.ch, ch_bytes)) != hipSuccess) {
+            return hip_fail(e, "hipMalloc(coefficient planes)");
+        }
         if ((e = hipMemsetAsync(I.u[0], 0, st_bytes, b.stream)) != hipSuccess ||
             (e = hipMemsetAsync(I.u[1], 0, st_bytes, b.stream)) != hipSuccess)
             return hip_fail(e, "hipMemset(state)");
@@ -230,6 +249,10 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
         J.ch = I.ch;
         J.cf = I.cf;
         J.wt = I.wt;
+        J.onfly = I.onfly;
+        J.rf = I.rf;
+        J.rh = I.rh;
+        J.trig = I.trig;
         if ((e = coef_pass(W, J, b.stream)) != hipSuccess) return hip_fail(e, "coefficient pass");
         std::memcpy(I.hdt, J.hdt, sizeof I.hdt);
         std::memcpy(I.dt, J.dt, sizeof I.dt);
@@ -443,6 +466,28 @@ int teuk_set_tile(teuk_t *h, int segcols) {
     return build_worklist(h->b);
 }
 
+static int set_launch(Batch &b, int segcols, int block) {
+    if (segcols < 1 || (block != 0 && block != 64 && block != 128 && block != 256))
+        return fail(TEUK_EINVAL, "segcols must be >= 1 and block one of 0, 64, 128, 256");
+    int maxnth = 0;
+    for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
+    if (block != 0 && block < maxnth) return fail(TEUK_EINVAL, "block must be >= n_theta");
+    if (int rc = check_ok(b)) return rc;
+    hipStreamSynchronize(b.stream);
+    b.segcols = segcols;
+    b.nt_req = block;
+    return build_worklist(b);
+}
+
+int teuk_set_launch(teuk_t *h, int segcols, int block) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_launch(h->b, segcols, block);
+}
+int teuk_batch_set_launch(teuk_batch_t *b, int segcols, int block) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_launch(b->b, segcols, block);
+}
+
 int teuk_check_finite(teuk_t *h, int *ok) {
     if (!h || !ok) return fail(TEUK_EINVAL, "NULL argument");
     Instance &I = h->b.inst[0];
@@ -473,12 +518,29 @@ int teuk_get_coefficients(teuk_t *h, int which, double *out) {
     }
     const int nr = which == 0 ? I.g.n_r - 1 : I.g.n_r;
     const double *src = which == 0 ? I.ch : I.cf;
-    const size_t plane = (size_t)nr * nth;
-    for (int c = 0; c < 8; ++c) {
-        int rc = download_planes(b, src + (size_t)c * W * plane, 1, nr, nth, W, out + (size_t)c * plane * W);
-        if (rc) return rc;
+    double *tmp = nullptr;
+    if (I.onfly) {
+        // FP64 kernels rebuild the coefficients per point: materialise them with the same routine
+        const size_t np = 8 * ((size_t)I.g.n_r + (I.g.n_r - 1)) * nth;
+        hipError_t e = hipMalloc((void **)&tmp, np * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(coefficient planes)");
+        double *cf = tmp, *ch = tmp + 8 * (size_t)I.g.n_r * nth;
+        e = lwk::fp64_planes(I.g.n_r, nth, I.rf, I.rh, I.trig, cf, ch, b.stream);
+        if (e != hipSuccess) {
+            hipFree(tmp);
+            return hip_fail(e, "coefficient planes");
+        }
+        src = which == 0 ? ch : cf;
     }
-    return TEUK_OK;
+    const size_t plane = (size_t)nr * nth;
+    int rc = TEUK_OK;
+    for (int c = 0; c < 8 && rc == TEUK_OK; ++c)
+        rc = download_planes(b, src + (size_t)c * W * plane, 1, nr, nth, W, out + (size_t)c * plane * W);
+    if (tmp) {
+        hipStreamSynchronize(b.stream);
+        hipFree(tmp);
+    }
+    return rc;
 }
 
 int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
@@ -487,6 +549,16 @@ int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
     if (int rc = check_ok(b)) return rc;
     Instance &I = b.inst[0];
     const int W = I.words, nth = I.g.n_theta;
+    if (I.onfly) {
+        // switch this instance to stored planes, seeded from its own per-point coefficients
+        hipError_t e = hipMalloc((void **)&I.cf, 8 * (size_t)I.g.n_r * nth * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void **)&I.ch, 8 * (size_t)(I.g.n_r - 1) * nth * sizeof(double));
+        if (e == hipSuccess) e = lwk::fp64_planes(I.g.n_r, nth, I.rf, I.rh, I.trig, I.cf, I.ch, b.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+        if (e != hipSuccess) return hip_fail(e, "coefficient planes");
+        I.onfly = 0;
+        if (int rc = build_worklist(b)) return rc;
+    }
     const int nr = which == 0 ? I.g.n_r - 1 : I.g.n_r;
     double *dst = which == 0 ? I.ch : I.cf;
     const size_t plane = (size_t)nr * nth;

@@ -52,6 +52,8 @@ _SIGS = {
     "teuk_set_stream": ([_P, _P], ctypes.c_int),
     "teuk_check_finite": ([_P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "teuk_set_tile": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_set_launch": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "teuk_batch_set_launch": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "teuk_get_coefficients": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "teuk_set_coefficients": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "teuk_batch_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _D,
@@ -162,6 +164,9 @@ class Teuk:
     def set_tile(self, segcols):
         _check(lib().teuk_set_tile(self.h, int(segcols)))
 
+    def set_launch(self, segcols, block=0):
+        _check(lib().teuk_set_launch(self.h, int(segcols), int(block)))
+
     def use_graph(self, k):
         _check(lib().teuk_use_graph(self.h, int(k)))
 
@@ -237,6 +242,9 @@ class TeukBatch:
 
     def set_tile(self, segcols):
         _check(lib().teuk_batch_set_tile(self.h, int(segcols)))
+
+    def set_launch(self, segcols, block=0):
+        _check(lib().teuk_batch_set_launch(self.h, int(segcols), int(block)))
 
     def use_graph(self, k):
         _check(lib().teuk_batch_use_graph(self.h, int(k)))

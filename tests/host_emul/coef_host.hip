@@ -16,10 +16,27 @@ static int run(CoefJob &J, double *ch, double *cf, double *wt) {
     std::vector<double> r((size_t)W * n), d((size_t)W * n), c((size_t)W * nth), s2((size_t)W * nth);
     for (int t = 0; t < n; ++t) coef_radial_one<T>(S.RP, t, S.rsmin, S.h, S.rp, S.dpm, S.A, S.B, r.data(), d.data());
     for (int j = 0; j < nth; ++j) coef_theta_one<T>(S.TP, j, S.dth, c.data(), s2.data(), wt);
-    for (int t = 0; t < n; ++t)
-        for (int j = 0; j < nth; ++j)
-            coef_point_one<T>(S.PP, t, j, r.data(), d.data(), c.data(), s2.data(), S.hdt, mp_mul(S.hdt, S.ih),
-                              S.dt, mp_mul(S.dt, S.ih), ch, cf);
+    if constexpr (W == 1) {
+        // FP64: the kernel rebuilds the coefficients per point from radial rows (as on the device)
+        const double sh = S.hdt, sih = mp_mul(S.hdt, S.ih), sf = S.dt, sif = mp_mul(S.dt, S.ih);
+        std::vector<double> row(kRadRow);
+        for (int t = 0; t < n; ++t) {
+            const bool half = t >= J.nr;
+            const int i = half ? t - J.nr : t, ni = half ? J.nr - 1 : J.nr;
+            coef_fp64_radial_row(J.s, J.m, J.mass, J.a_over_M * J.mass, r[t], d[t], half ? sh : sf, half ? sih : sif,
+                                 row.data());
+            for (int j = 0; j < nth; ++j) {
+                double cc[8];
+                coef_fp64_point(row.data(), c[j], s2[j], cc);
+                for (int k = 0; k < 8; ++k) (half ? ch : cf)[(size_t)k * ni * nth + (size_t)i * nth + j] = cc[k];
+            }
+        }
+    } else {
+        for (int t = 0; t < n; ++t)
+            for (int j = 0; j < nth; ++j)
+                coef_point_one<T>(S.PP, t, j, r.data(), d.data(), c.data(), s2.data(), S.hdt, mp_mul(S.hdt, S.ih),
+                                  S.dt, mp_mul(S.dt, S.ih), ch, cf);
+    }
     return 0;
 }
 
