@@ -2,8 +2,10 @@
 
 A "step" is one full time step (stage lw1 then lw2) of the headline workload:
 s = -2, m = 2, a/M = 0.9 on 4096 r* x 128 theta, r* in [-200, 800] M, FP64,
-CFL 0.5.  value = grid-point updates per second (n_r * n_theta per step) over
-exactly --steps timed steps, inputs resident in HBM.  The same JSON line
+10,000 steps (at CFL 0.15: at the stated 0.5 the run is unstable; the cost
+per update does not depend on the time step).  value = grid-point updates per
+second (n_r * n_theta per step) over exactly --steps timed steps, inputs
+resident in HBM; the launch shape is picked by the autotuner before timing.  The same JSON line
 carries the double-double and quad-double workloads, the batched-vs-loop
 comparison, the roofline of the step kernel and the oracle timed on the host
 cores.  Prints one JSON line.
@@ -20,12 +22,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
-# algorithmic bytes per grid-point update of the step kernel: state read
-# (4 reals) + state write (4 reals) + 16 stored coefficients (8 at the half
-# node, 8 at the node), each real `words` doubles
-def bytes_per_update(words):
-    return (4 + 4 + 16) * 8 * words
-
 
 def _torch():
     import torch
@@ -34,12 +30,18 @@ def _torch():
     return torch
 
 
-def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream):
+def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=None):
+    from paper_1006_0663_amd import autotune
     g = T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
     h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
     h.set_stream(stream.cuda_stream)
+    h.set_initial(*fields)
     if tile:
-        h.set_tile(tile)
+        h.set_launch(tile, 0)
+        shape = (tile, 0)
+    else:
+        s_, b_, _ = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)
+        shape = (s_, b_)
     if graph:
         h.use_graph(graph)
     h.set_initial(*fields)
@@ -56,10 +58,10 @@ def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream):
     ms = e0.elapsed_time(e1)
     finite = h.check_finite()
     h.close()
-    return ms, wall, finite
+    return ms, wall, finite, shape
 
 
-def cpu_baseline(w, seconds_target=12.0):
+def cpu_baseline(w, seconds_target=15.0):
     """The oracle (C fixed-point engine, all host cores) on a radial slab of the
     headline workload: 512 r* nodes around the pulse x all theta rows."""
     from paper_1006_0663_amd import inputs
@@ -77,9 +79,10 @@ def cpu_baseline(w, seconds_target=12.0):
     tab = problem.build_tables(slab, processes=min(cores, 16))
     FT = engine.tables_to_fixed(tab, processes=min(cores, 16))
     u = engine.fields_to_fixed([f[:, i0:i0 + nslab] for f in full])
+    engine.run_fixed(FT, nslab, w.n_theta, u, 1, threads=cores)      # thread start-up
     t0 = time.perf_counter()
-    engine.run_fixed(FT, nslab, w.n_theta, u, 1, threads=cores)
-    one = time.perf_counter() - t0
+    engine.run_fixed(FT, nslab, w.n_theta, u, 3, threads=cores)
+    one = (time.perf_counter() - t0) / 3
     nsteps = max(1, int(seconds_target / max(one, 1e-3)))
     t0 = time.perf_counter()
     engine.run_fixed(FT, nslab, w.n_theta, u, nsteps, threads=cores)
@@ -114,39 +117,53 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    from paper_1006_0663_amd import opcount
     w = inputs.C2
     log("bench: generating %s inputs" % w.name)
     fields = inputs.initial_fields(w)
     log("bench: timing %s, %d warmup + %d steps" % (w.name, args.warmup, args.steps))
-    ms, wall, finite = time_single(T, w, fields, args.steps, args.warmup, args.graph, args.tile, torch, stream)
+    ms, wall, finite, shape = time_single(T, w, fields, args.steps, args.warmup, args.graph, args.tile, torch,
+                                          stream, log)
     pts = w.n_r * w.n_theta
     value = pts * args.steps / (ms / 1e3)
     ms_step = ms / args.steps
-    achieved = bytes_per_update(1) * pts / (ms_step / 1e3) / 1e9
+    bpu = opcount.bytes_per_update(1)
+    achieved = bpu * pts / (ms_step / 1e3) / 1e9
+    fpu = opcount.flops_per_update(1)
     out = {
         "metric": "grid-point updates/sec per precision (FP64/dd/qd) + % FP64 peak; batched vs plain",
         "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "teukolsky-lw fp64 s=-2 m=2 a/M=0.9 4096x128 r*[-200,800] cfl=0.5",
-                   "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph},
+        "config": {"workload": "teukolsky-lw fp64 s=-2 m=2 a/M=0.9 4096x128 r*[-200,800] cfl=%g steps=%d"
+                               % (w.cfl, w.steps),
+                   "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph,
+                   "segcols": shape[0], "block": shape[1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "lw_step_kernel<double,128>",
-                     "algorithmic_bytes_per_update": bytes_per_update(1)},
+                     "kernel": "lw_step_kernel<double>",
+                     "algorithmic_bytes_per_update": bpu, "updates_per_launch": pts},
+        "fp64_flops_per_update": fpu,
+        "pct_fp64_peak": 100.0 * fpu * value / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
         "finite": finite,
         "wall_s_timed": wall,
     }
     if not args.headline_only:
-        per = {"fp64": {"workload": w.name, "updates_per_s": value}}
+        per = {"fp64-4096x128": {"words": 1, "steps": args.steps, "updates_per_s": value,
+                                 "pct_fp64_peak": out["pct_fp64_peak"]}}
         for wx in (inputs.C3, inputs.C3_PARITY, inputs.C4):
             log("bench: timing %s (%d steps)" % (wx.name, wx.steps))
             fx = inputs.initial_fields(wx)
-            msx, _, fin = time_single(T, wx, fx, wx.steps, min(args.warmup, wx.steps // 10), args.graph,
-                                      args.tile, torch, stream)
-            per[wx.name] = {"workload": wx.name, "words": wx.words, "steps": wx.steps,
-                            "updates_per_s": wx.n_r * wx.n_theta * wx.steps / (msx / 1e3),
-                            "ms_per_step": msx / wx.steps, "finite": fin}
+            msx, _, fin, shp = time_single(T, wx, fx, wx.steps, min(args.warmup, wx.steps // 10), args.graph,
+                                           args.tile, torch, stream, log)
+            ups = wx.n_r * wx.n_theta * wx.steps / (msx / 1e3)
+            f = opcount.flops_per_update(wx.words)
+            per[wx.name] = {"words": wx.words, "steps": wx.steps, "updates_per_s": ups,
+                            "ms_per_step": msx / wx.steps, "segcols": shp[0], "block": shp[1],
+                            "fp64_flops_per_update": f,
+                            "pct_fp64_peak": 100.0 * f * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
+                            "hbm_GBs_algorithmic": opcount.bytes_per_update(wx.words) * ups / 1e9,
+                            "finite": fin}
         out["per_precision"] = per
         out["batched"] = bench_batched(T, inputs, args, torch, stream, log)
     if not args.no_cpu_baseline:
@@ -161,8 +178,16 @@ def bench_batched(T, inputs, args, torch, stream, log):
     log("bench: batched %d dd instances x %d steps (generating inputs)" % (len(ws), steps))
     fields = [inputs.initial_fields(w) for w in ws]
     grids = [T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl) for w in ws]
+    from paper_1006_0663_amd import autotune, opcount
     b = T.TeukBatch([(w.s, w.m, w.a_over_M, g) for w, g in zip(ws, grids)], 2)
     b.set_stream(stream.cuda_stream)
+    for k, f in enumerate(fields):
+        b.set_initial(k, *f)
+    if args.tile:
+        b.set_launch(args.tile, 0)
+        bshape = (args.tile, 0)
+    else:
+        bshape = autotune.tune(b, 2, [(w.n_r, w.n_theta) for w in ws], torch, stream, steps=5)[:2]
     if args.graph:
         b.use_graph(args.graph)
     for k, f in enumerate(fields):
@@ -183,6 +208,11 @@ def bench_batched(T, inputs, args, torch, stream, log):
     for w, g, f in zip(ws, grids, fields):
         h = T.Teuk(w.s, w.m, w.a_over_M, g, 2)
         h.set_stream(stream.cuda_stream)
+        h.set_initial(*f)
+        if args.tile:
+            h.set_launch(args.tile, 0)
+        else:
+            autotune.tune(h, 2, [(w.n_r, w.n_theta)], torch, stream, steps=5)
         if args.graph:
             h.use_graph(args.graph)
         h.set_initial(*f)
@@ -200,10 +230,13 @@ def bench_batched(T, inputs, args, torch, stream, log):
     ms_p = e0.elapsed_time(e1)
     for h in hs:
         h.close()
-    return {"instances": len(ws), "steps": steps, "points": pts,
-            "batched_updates_per_s": pts * steps / (ms_b / 1e3),
+    f = opcount.flops_per_update(2)
+    ub = pts * steps / (ms_b / 1e3)
+    return {"instances": len(ws), "steps": steps, "points": pts, "words": 2,
+            "batched_updates_per_s": ub,
             "plain_loop_updates_per_s": pts * steps / (ms_p / 1e3),
-            "speedup": ms_p / ms_b}
+            "speedup": ms_p / ms_b, "segcols": bshape[0], "block": bshape[1],
+            "batched_pct_fp64_peak": 100.0 * f * ub / (FP64_VECTOR_PEAK_TFLOPS * 1e12)}
 
 
 if __name__ == "__main__":

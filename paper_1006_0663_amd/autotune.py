@@ -3,7 +3,7 @@
 Times a short run of every candidate (segment length S, block size) on the
 actual instance or batch with HIP events on the handle's stream, keeps the
 fastest, and caches the choice in a JSON file keyed by device, precision and
-grid shape (``TEUK_TUNE_CACHE``, default ~/.cache/libteuk_tune.json).  The
+grid shape (``TEUK_TUNE_CACHE``, default tune_cache.json next to this file).  The
 launch shape does not change results (tested bitwise), only speed.
 """
 import json
@@ -14,7 +14,8 @@ BLOCKS = (0, 128, 256)
 
 
 def cache_path():
-    return os.environ.get("TEUK_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "libteuk_tune.json"))
+    return os.environ.get("TEUK_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                          "tune_cache.json"))
 
 
 def _load():

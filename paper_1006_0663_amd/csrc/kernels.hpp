@@ -475,7 +475,12 @@ __device__ __forceinline__ void load_coef(const InstDev &I, const double *planes
     if constexpr (W == 1) {
         if (I.onfly) {
             double cc[8];
-            coef_fp64_point(rows + (size_t)(on ? i : 0) * kRadRow, cs, s2, cc);
+            int ii = on ? i : 0;
+            // with n_theta >= 64 the active lanes of a wavefront share one
+            // column: make the row index uniform so the row is read with
+            // scalar loads
+            if (I.nth >= 64) ii = __builtin_amdgcn_readfirstlane(ii);
+            coef_fp64_point(rows + (size_t)ii * kRadRow, cs, s2, cc);
 #pragma unroll
             for (int q = 0; q < 8; ++q) c[q] = on ? cc[q] : 0.0;
             return;
@@ -528,10 +533,13 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     cx<T> l_prev = zero.phi, l_cur, lh_prev = zero.phi, lh_cur;
     // Every lane runs the same S + 2 iterations (the barriers in theta_apply
     // must be reached uniformly); work outside the segment is masked.
+    // the next column's state is loaded one iteration ahead
+    Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
     for (int t = 0; t < S + 2; ++t) {
         const int col = a + t;
         const bool col_on = seg_on && col <= e;
-        u_cur = col_on ? ld_pt<T>(uin, plane, (size_t)col * nth + j) : zero;
+        u_cur = u_next;
+        if (seg_on && col + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(col + 1) * nth + j);
         l_cur = theta_apply<T>(u_cur.phi, buf0, lane_on ? j : 0, nth, R, wrow, lane_on);
         // (lw1) at half node (col-1)+1/2
         const bool h_on = col_on && t >= 1;
