@@ -64,10 +64,14 @@ enum {
     kVp2, kA2D, kVp, kSD, kSIVp, kST1, kST2, kST3, kST4, kST5, kSIT1, kSIT2, kSIT3, kSIT6, kSIT7, kSIT8
 };
 
-// 1/sqrt(x), x > 0: correctly rounded float seed, two Newton steps in double
-// (same basic operations on host and device, so both give the same bits)
+// 1/sqrt(x), x > 0, to about one ulp: the hardware reciprocal square root
+// seeds two Newton steps on the device; the host starts from 1/sqrt(x).
 MPA double rsqrt_nr(double x) {
-    double y = (double)(1.0f / sqrtf((float)x));
+#ifdef __HIP_DEVICE_COMPILE__
+    double y = __builtin_amdgcn_rsq(x);
+#else
+    double y = 1.0 / sqrt(x);
+#endif
     const double hx = 0.5 * x;
     y = y * fma(-hx, y * y, 1.5);
     y = y * fma(-hx, y * y, 1.5);
@@ -434,68 +438,118 @@ template <class T> MPA cx<T> c_diff(const cx<T> &a, const cx<T> &b) {     // b -
 template <class T> MPA Pt<T> pt_avg(const Pt<T> &a, const Pt<T> &b) { return {c_avg(a.phi, b.phi), c_avg(a.pi, b.pi)}; }
 template <class T> MPA Pt<T> pt_diff(const Pt<T> &a, const Pt<T> &b) { return {c_diff(a.phi, b.phi), c_diff(a.pi, b.pi)}; }
 
-// Angular operator of the value v held by lane j of a group, via the LDS
-// buffer buf.  Callers alternate strictly between two buffers, so the single
-// barrier between the write and the reads also orders this write after every
-// lane's reads of the same buffer two exchanges earlier.
-template <class T>
-__device__ __forceinline__ cx<T> theta_apply(cx<T> v, cx<T> *buf, int j, int nth, int reach,
-                                             const double *__restrict__ wt, bool active) {
+// ---- LDS exchange of theta columns
+// A complex value of T is 2W doubles, stored as W 16-byte chunks, each chunk
+// in its own [lane] array: consecutive lanes touch consecutive 16-byte words,
+// so a 16-byte read per lane is free of bank conflicts for every W.
+struct __align__(16) d2 {
+    double a, b;
+};
+
+template <class T> __device__ __forceinline__ void xput(d2 *base, int stride, int slot, const cx<T> &v) {
     constexpr int W = words_of<T>::value;
-    if (active) buf[j] = v;
-    __syncthreads();
-    Acc<T> re, im;
-    auto tap = [&](int k) {
-        int q = j + k;
-        q = q < 0 ? -1 - q : (q >= nth ? 2 * nth - 1 - q : q);
-        const cx<T> x = buf[q];
-        const T w = ld<T>(wt + (size_t)(k + reach) * W * nth, (size_t)nth, (size_t)j);
-        re.prod(w, x.re);
-        im.prod(w, x.im);
-    };
     if constexpr (W == 1) {
-        // double: unrolled, all loads issued together
-#pragma unroll
-        for (int k = -kMaxReach; k <= kMaxReach; ++k)
-            if (k >= -reach && k <= reach) tap(k);
+        base[slot] = {v.re, v.im};
     } else {
-        // multiword: a rolled loop keeps only one tap's operands live
+#pragma unroll
+        for (int c = 0; c < W / 2; ++c) {
+            base[(size_t)c * stride + slot] = {mp_word(v.re, 2 * c), mp_word(v.re, 2 * c + 1)};
+            base[(size_t)(c + W / 2) * stride + slot] = {mp_word(v.im, 2 * c), mp_word(v.im, 2 * c + 1)};
+        }
+    }
+}
+template <class T> __device__ __forceinline__ cx<T> xget(const d2 *base, int stride, int slot) {
+    constexpr int W = words_of<T>::value;
+    cx<T> v;
+    if constexpr (W == 1) {
+        const d2 x = base[slot];
+        v.re = x.a;
+        v.im = x.b;
+    } else {
+#pragma unroll
+        for (int c = 0; c < W / 2; ++c) {
+            const d2 x = base[(size_t)c * stride + slot], y = base[(size_t)(c + W / 2) * stride + slot];
+            mp_set_word(v.re, 2 * c, x.a);
+            mp_set_word(v.re, 2 * c + 1, x.b);
+            mp_set_word(v.im, 2 * c, y.a);
+            mp_set_word(v.im, 2 * c + 1, y.b);
+        }
+    }
+    return v;
+}
+
+// Reflected source row of tap k for row j (ghost rows mirror across the pole).
+__device__ __forceinline__ int tap_row(int j, int k, int nth) {
+    const int q = j + k;
+    return q < 0 ? -1 - q : (q >= nth ? 2 * nth - 1 - q : q);
+}
+
+// Angular operator at row j of the column held in an exchange buffer (group
+// base `base`, chunk stride `stride`): folded weights of row j times the
+// reflected rows, as one fused dot product per component.  For double the
+// weights (w) and source rows (qrow) of the lane are held in registers; the
+// multiword types read the weights from the table and use a rolled loop.
+template <class T>
+__device__ __forceinline__ cx<T> theta_stencil(const d2 *base, int stride, int j, int nth, int reach,
+                                               const double *__restrict__ wt, const double *w, const int *qrow) {
+    constexpr int W = words_of<T>::value;
+    Acc<T> re, im;
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
+            if (k < kMaxReach - reach || k > kMaxReach + reach) continue;
+            const cx<T> x = xget<T>(base, stride, qrow[k]);
+            re.prod(w[k], x.re);
+            im.prod(w[k], x.im);
+        }
+    } else {
 #pragma unroll 1
-        for (int k = -reach; k <= reach; ++k) tap(k);
+        for (int k = -reach; k <= reach; ++k) {
+            const cx<T> x = xget<T>(base, stride, tap_row(j, k, nth));
+            const T wk = ld<T>(wt + (size_t)(k + reach) * W * nth, (size_t)nth, (size_t)j);
+            re.prod(wk, x.re);
+            im.prod(wk, x.im);
+        }
     }
     return {re.result(), im.result()};
 }
 
 // eight coefficients of node/half node i at row j: from the stored planes, or
-// (FP64 with onfly) rebuilt from the radial row and the row's cos, sin^2
+// (FP64 per-point mode) rebuilt from the radial row staged in LDS
 template <class T>
-__device__ __forceinline__ void load_coef(const InstDev &I, const double *planes, const double *rows,
-                                          size_t plane, bool on, int i, int j, double cs, double s2, T *c) {
+__device__ __forceinline__ void load_coef(const InstDev &I, const double *planes, const double *lrow, size_t plane,
+                                          bool on, int i, int j, double cs, double s2, T *c) {
     constexpr int W = words_of<T>::value;
     if constexpr (W == 1) {
         if (I.onfly) {
-            double cc[8];
-            int ii = on ? i : 0;
-            // with n_theta >= 64 the active lanes of a wavefront share one
-            // column: make the row index uniform so the row is read with
-            // scalar loads
-            if (I.nth >= 64) ii = __builtin_amdgcn_readfirstlane(ii);
-            coef_fp64_point(rows + (size_t)ii * kRadRow, cs, s2, cc);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) c[q] = on ? cc[q] : 0.0;
+            coef_fp64_point(lrow, cs, s2, c);
             return;
         }
     }
+    (void)on;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        c[q] = on ? ld<T>(planes + (size_t)q * W * plane, plane, (size_t)i * I.nth + j) : mp_from<T>(0.0);
+    for (int q = 0; q < 8; ++q) c[q] = ld<T>(planes + (size_t)q * W * plane, plane, (size_t)i * I.nth + j);
 }
 
+// LDS bytes the FP64 per-point mode needs for a block of NT threads
+MPA size_t rows_lds_bytes(int nt, int nth, int segcols) {
+    const int G = nt / nth;
+    return (size_t)(2 * G * segcols + 3) * kRadRow * sizeof(double);
+}
+
+// One full step (lw1 + lw2) of every work item.  A group of n_theta lanes
+// sweeps the r* nodes a..e of its segment.  Iteration k handles column
+// c = a + k: one LDS exchange carries both u^n at column c and the half-step
+// value at c - 3/2 (computed in iteration k-1), so each column costs one
+// barrier; then stage 2 at node c - 2 and stage 1 at half node c - 1/2.
+// Double-buffered exchange slots make one barrier per iteration sufficient.
 template <class T, int NT>
 __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__ insts,
                                                      const WorkItem *__restrict__ items, int parity) {
     constexpr int W = words_of<T>::value;
-    __shared__ cx<T> lds[2][NT];
+    constexpr int CH = W == 1 ? 1 : W;                 // 16-byte chunks per complex value
+    __shared__ d2 xb[2][2][CH][NT];                    // [set][P = u^n, H = half step][chunk][lane]
+    extern __shared__ double lrows[];                  // FP64 per-point mode: radial rows of the block
     const WorkItem wi = items[blockIdx.x];
     const InstDev &I = insts[wi.inst];
     const int nr = I.nr, nth = I.nth, R = I.reach, S = I.segcols;
@@ -509,63 +563,129 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     double *uout = I.u[parity ^ 1];
     const size_t plane = (size_t)nr * nth, hplane = (size_t)(nr - 1) * nth;
     const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
+    const int slot = lane_on ? g * nth + j : j;          // idle lanes never write
+    const int gbase = lane_on ? g * nth : 0;
 
-    // angular weights of this row (wt + tap * W * nth); rows of idle lanes read row 0
-    const double *wrow = I.wt;
-    cx<T> *buf0 = &lds[0][lane_on ? g * nth : 0], *buf1 = &lds[1][lane_on ? g * nth : 0];
+    // FP64 per-point mode: stage the block's radial rows in LDS
+    const int bnA = max(wi.group * G * S, 1) - 1;
+    const int bnB = min((wi.group * G + G) * S, nr - 1);
+    double *lrow_f = lrows, *lrow_h = lrows + (size_t)(bnB - bnA + 1) * kRadRow;
+    double cs_j = 0.0, s2_j = 0.0;
+    if constexpr (W == 1) {
+        if (I.onfly) {
+            const int nf = (bnB - bnA + 1) * kRadRow, nh = (bnB - bnA) * kRadRow;
+            for (int q = threadIdx.x; q < nf + nh; q += NT)
+                lrows[q] = q < nf ? I.rf[(size_t)bnA * kRadRow + q] : I.rh[(size_t)bnA * kRadRow + (q - nf)];
+            if (lane_on) {
+                cs_j = I.trig[j];
+                s2_j = I.trig[nth + j];
+            }
+        }
+    }
+
+    // double: this row's weights and reflected source rows in registers
+    double wreg[2 * kMaxReach + 1];
+    int qrow[2 * kMaxReach + 1];
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
+            const int kk = k - kMaxReach;
+            const bool tap_on = lane_on && kk >= -R && kk <= R;
+            wreg[k] = tap_on ? I.wt[(size_t)(kk + R) * nth + j] : 0.0;
+            qrow[k] = tap_on ? tap_row(j, kk, nth) : 0;
+        }
+    }
 
     // zero radial boundary nodes owned by this segment
+    const Pt<T> zero = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
     if (seg_on) {
-        const Pt<T> z = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
-        if (c0 == 0) st_pt(uout, plane, (size_t)j, z);
-        if (c1 == nr) st_pt(uout, plane, (size_t)(nr - 1) * nth + j, z);
-    }
-    // theta factors of this row for the FP64 per-point coefficients
-    double cs_j = 0.0, s2_j = 0.0;
-    if (words_of<T>::value == 1 && I.onfly && lane_on) {
-        cs_j = I.trig[j];
-        s2_j = I.trig[nth + j];
+        if (c0 == 0) st_pt(uout, plane, (size_t)j, zero);
+        if (c1 == nr) st_pt(uout, plane, (size_t)(nr - 1) * nth + j, zero);
     }
     const int a = max(c0, 1) - 1;          // first node read
-    const int e = min(c1, nr - 1);         // interior outputs are nodes a+1 .. e-1
-    const Pt<T> zero = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
-    Pt<T> u_prev = zero, u_cur, uh_prev = zero, uh_cur;
-    cx<T> l_prev = zero.phi, l_cur, lh_prev = zero.phi, lh_cur;
-    // Every lane runs the same S + 2 iterations (the barriers in theta_apply
-    // must be reached uniformly); work outside the segment is masked.
-    // the next column's state is loaded one iteration ahead
-    Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
-    for (int t = 0; t < S + 2; ++t) {
-        const int col = a + t;
-        const bool col_on = seg_on && col <= e;
-        u_cur = u_next;
-        if (seg_on && col + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(col + 1) * nth + j);
-        l_cur = theta_apply<T>(u_cur.phi, buf0, lane_on ? j : 0, nth, R, wrow, lane_on);
-        // (lw1) at half node (col-1)+1/2
-        const bool h_on = col_on && t >= 1;
-        T c[8];
-        load_coef<T>(I, I.ch, I.rh, hplane, h_on, col - 1, j, cs_j, s2_j, c);
-        {
+    const int e = min(c1, nr - 1);         // nodes a..e read; outputs a+1 .. e-1
+    if constexpr (W == 4) {
+        // quad-double: two exchanges per column (u^n, then the half step) with
+        // the stages in sequence, which keeps fewer quad-double values live
+        Pt<T> u_prev = zero, uh_prev = zero;
+        cx<T> l_prev = zero.phi, lh_prev = zero.phi;
+        Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
+        d2 *xp = &xb[0][0][0][0], *xh = &xb[0][1][0][0];
+        for (int t = 0; t < S + 2; ++t) {
+            const int col = a + t;
+            const Pt<T> u_cur = u_next;
+            if (seg_on && col + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(col + 1) * nth + j);
+            if (lane_on) xput<T>(xp, NT, slot, u_cur.phi);
+            __syncthreads();
+            const cx<T> l_cur = theta_stencil<T>(xp + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+            // (lw1) at half node col-1/2 (index col-1)
+            const bool h_on = seg_on && col <= e && t >= 1;
+            T cf[8];
+            load_coef<T>(I, I.ch, nullptr, hplane, h_on, min(max(col - 1, 0), nr - 2), j, 0.0, 0.0, cf);
             const Pt<T> bar = pt_avg(u_prev, u_cur);
-            const Pt<T> d = pt_diff(u_prev, u_cur);
-            const cx<T> lbar = c_avg(l_prev, l_cur);
-            uh_cur = lw_stage(bar, bar, d, lbar, c, hdt);
+            const Pt<T> uh_cur = lw_stage(bar, bar, pt_diff(u_prev, u_cur), c_avg(l_prev, l_cur), cf, hdt);
+            if (lane_on) xput<T>(xh, NT, slot, uh_cur.phi);
+            __syncthreads();
+            const cx<T> lh_cur = theta_stencil<T>(xh + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+            if (h_on && t >= 2) {
+                // (lw2) at node col-1
+                const int i = col - 1;
+                load_coef<T>(I, I.cf, nullptr, plane, true, i, j, 0.0, 0.0, cf);
+                const Pt<T> un = lw_stage(u_prev, pt_avg(uh_prev, uh_cur), pt_diff(uh_prev, uh_cur),
+                                          c_avg(lh_prev, lh_cur), cf, dt);
+                st_pt(uout, plane, (size_t)i * nth + j, un);
+            }
+            u_prev = u_cur;
+            l_prev = l_cur;
+            uh_prev = uh_cur;
+            lh_prev = lh_cur;
         }
-        lh_cur = theta_apply<T>(uh_cur.phi, buf1, lane_on ? j : 0, nth, R, wrow, lane_on);
-        if (h_on && t >= 2) {
-            // (lw2) at node col-1
-            const int i = col - 1;
-            load_coef<T>(I, I.cf, I.rf, plane, true, i, j, cs_j, s2_j, c);
-            const Pt<T> barh = pt_avg(uh_prev, uh_cur);
-            const Pt<T> dh = pt_diff(uh_prev, uh_cur);
-            const cx<T> lbarh = c_avg(lh_prev, lh_cur);
-            const Pt<T> un = lw_stage(u_prev, barh, dh, lbarh, c, dt);
-            st_pt(uout, plane, (size_t)i * nth + j, un);
+        return;
+    }
+    Pt<T> u_m2 = zero, u_m1 = zero;        // u^n at c-2, c-1
+    Pt<T> uh_m52 = zero, uh_m32 = zero;    // half-step values at c-5/2, c-3/2
+    cx<T> l_m1 = zero.phi, lh_m52 = zero.phi;
+    Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
+    for (int k = 0; k < S + 3; ++k) {
+        const int c = a + k;
+        const Pt<T> u_c = u_next;
+        if (seg_on && c + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(c + 1) * nth + j);
+        d2 *xp = &xb[k & 1][0][0][0], *xh = &xb[k & 1][1][0][0];
+        if (lane_on) {
+            xput<T>(xp, NT, slot, u_c.phi);
+            xput<T>(xh, NT, slot, uh_m32.phi);
         }
-        uh_prev = uh_cur;
-        lh_prev = lh_cur;
-        u_prev = u_cur;
-        l_prev = l_cur;
+        __syncthreads();
+        const cx<T> l_c = theta_stencil<T>(xp + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+        const cx<T> lh_m32 = theta_stencil<T>(xh + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+        T cf[8];
+        if (k >= 3) {
+            // (lw2) at node c-2; indices are clamped so inactive lanes read valid memory
+            const int i = c - 2;
+            const bool on = seg_on && i <= e - 1;
+            const int ic = min(max(i, 1), nr - 2);
+            load_coef<T>(I, I.cf, lrow_f + (size_t)min(max(i - bnA, 0), bnB - bnA) * kRadRow, plane, on, ic, j,
+                         cs_j, s2_j, cf);
+            const Pt<T> un = lw_stage(u_m2, pt_avg(uh_m52, uh_m32), pt_diff(uh_m52, uh_m32), c_avg(lh_m52, lh_m32),
+                                      cf, dt);
+            if (on) st_pt(uout, plane, (size_t)i * nth + j, un);
+        }
+        Pt<T> uh_new = zero;
+        if (k >= 1) {
+            // (lw1) at half node c-1/2 (index c-1)
+            const bool on = seg_on && c <= e;
+            const int hc = min(max(c - 1, 0), nr - 2);
+            load_coef<T>(I, I.ch, lrow_h + (size_t)min(max(c - 1 - bnA, 0), bnB - bnA - 1) * kRadRow, hplane, on, hc,
+                         j, cs_j, s2_j, cf);
+            const Pt<T> bar = pt_avg(u_m1, u_c);
+            uh_new = lw_stage(bar, bar, pt_diff(u_m1, u_c), c_avg(l_m1, l_c), cf, hdt);
+        }
+        u_m2 = u_m1;
+        u_m1 = u_c;
+        l_m1 = l_c;
+        uh_m52 = uh_m32;
+        lh_m52 = lh_m32;
+        uh_m32 = uh_new;
     }
 }
 

@@ -120,13 +120,13 @@ hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
 }
 
 template <class T>
-hipError_t step_launch(int nt, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_launch(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                        hipStream_t stream) {
     if (nitems <= 0) return hipSuccess;
     switch (nt) {
-        case 64: lw_step_kernel<T, 64><<<nitems, 64, 0, stream>>>(insts, items, parity); break;
-        case 128: lw_step_kernel<T, 128><<<nitems, 128, 0, stream>>>(insts, items, parity); break;
-        case 256: lw_step_kernel<T, 256><<<nitems, 256, 0, stream>>>(insts, items, parity); break;
+        case 64: lw_step_kernel<T, 64><<<nitems, 64, lds, stream>>>(insts, items, parity); break;
+        case 128: lw_step_kernel<T, 128><<<nitems, 128, lds, stream>>>(insts, items, parity); break;
+        case 256: lw_step_kernel<T, 256><<<nitems, 256, lds, stream>>>(insts, items, parity); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -20,6 +20,8 @@ namespace {
 
 thread_local std::string g_err;
 
+constexpr size_t kMaxRowsLds = 40 * 1024;
+
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
@@ -77,6 +79,7 @@ struct Batch {
     int segcols = 8;
     int nt = 64;
     int nt_req = 0;          // requested block size (0 = smallest that fits)
+    size_t lds = 0;          // dynamic LDS bytes per block of the step kernel
     lwk::InstDev *d_inst = nullptr;
     lwk::WorkItem *d_items = nullptr;
     int nitems = 0;
@@ -129,9 +132,9 @@ hipError_t coef_pass(int words, lwk::CoefJob &job, hipStream_t st) {
 
 hipError_t step_launch(const Batch &b, int parity) {
     switch (b.words) {
-        case 1: return lwk::step_f64(b.nt, b.d_inst, b.d_items, b.nitems, parity, b.stream);
-        case 2: return lwk::step_dd(b.nt, b.d_inst, b.d_items, b.nitems, parity, b.stream);
-        default: return lwk::step_qd(b.nt, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        case 1: return lwk::step_f64(b.nt, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        case 2: return lwk::step_dd(b.nt, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        default: return lwk::step_qd(b.nt, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
     }
 }
 
@@ -141,6 +144,19 @@ int build_worklist(Batch &b) {
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     b.nt = maxnth <= 64 ? 64 : (maxnth <= 128 ? 128 : 256);
     if (b.nt_req > b.nt) b.nt = b.nt_req;
+    // FP64 per-point mode stages the radial rows of a block in LDS: keep that
+    // within kMaxRowsLds by shortening the segments if needed
+    b.lds = 0;
+    for (;;) {
+        size_t need = 0;
+        for (auto &I : b.inst)
+            if (I.onfly) need = std::max(need, lwk::rows_lds_bytes(b.nt, I.g.n_theta, b.segcols));
+        if (need <= kMaxRowsLds || b.segcols == 1) {
+            b.lds = need;
+            break;
+        }
+        b.segcols -= 1;
+    }
     std::vector<lwk::InstDev> hd(b.inst.size());
     std::vector<lwk::WorkItem> items;
     // largest instances first
