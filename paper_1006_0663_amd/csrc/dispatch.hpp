@@ -29,12 +29,13 @@ hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, cons
                        double *ch, hipStream_t stream);
 
 // One step of every work item: block size nt in {64, 128, 256}.
+// seg = segment length (r* nodes per work item, as in the descriptors);
 // lds = dynamic LDS bytes (radial rows of the FP64 per-point mode, else 0).
-hipError_t step_f64(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_f64(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                     hipStream_t stream);
-hipError_t step_dd(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_dd(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream);
-hipError_t step_qd(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_qd(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream);
 
 }  // namespace lwk

@@ -543,16 +543,19 @@ MPA size_t rows_lds_bytes(int nt, int nth, int segcols) {
 // value at c - 3/2 (computed in iteration k-1), so each column costs one
 // barrier; then stage 2 at node c - 2 and stage 1 at half node c - 1/2.
 // Double-buffered exchange slots make one barrier per iteration sufficient.
-template <class T, int NT>
+template <class T, int NT, int SEG>
 __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__ insts,
                                                      const WorkItem *__restrict__ items, int parity) {
+    // SEG > 0: the segment length is a compile-time constant (must equal the
+    // descriptor's segcols); the sweep is then fully unrolled and every
+    // column of the segment is requested from memory up front.
     constexpr int W = words_of<T>::value;
     constexpr int CH = W == 1 ? 1 : W;                 // 16-byte chunks per complex value
     __shared__ d2 xb[2][2][CH][NT];                    // [set][P = u^n, H = half step][chunk][lane]
     extern __shared__ double lrows[];                  // FP64 per-point mode: radial rows of the block
     const WorkItem wi = items[blockIdx.x];
     const InstDev &I = insts[wi.inst];
-    const int nr = I.nr, nth = I.nth, R = I.reach, S = I.segcols;
+    const int nr = I.nr, nth = I.nth, R = I.reach, S = SEG > 0 ? SEG : I.segcols;
     const int G = NT / nth;
     const int g = threadIdx.x / nth, j = threadIdx.x - g * nth;
     const bool lane_on = g < G;
@@ -645,11 +648,9 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     Pt<T> u_m2 = zero, u_m1 = zero;        // u^n at c-2, c-1
     Pt<T> uh_m52 = zero, uh_m32 = zero;    // half-step values at c-5/2, c-3/2
     cx<T> l_m1 = zero.phi, lh_m52 = zero.phi;
-    Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
-    for (int k = 0; k < S + 3; ++k) {
+    // one column: exchange, stencils, stage 2 at c-2, stage 1 at c-1/2
+    auto column = [&](int k, const Pt<T> &u_c) {
         const int c = a + k;
-        const Pt<T> u_c = u_next;
-        if (seg_on && c + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(c + 1) * nth + j);
         d2 *xp = &xb[k & 1][0][0][0], *xh = &xb[k & 1][1][0][0];
         if (lane_on) {
             xput<T>(xp, NT, slot, u_c.phi);
@@ -686,6 +687,21 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         uh_m52 = uh_m32;
         lh_m52 = lh_m32;
         uh_m32 = uh_new;
+    };
+    if constexpr (SEG > 0) {
+        Pt<T> ucol[SEG + 2];
+#pragma unroll
+        for (int q = 0; q < SEG + 2; ++q)
+            ucol[q] = (seg_on && a + q <= e) ? ld_pt<T>(uin, plane, (size_t)(a + q) * nth + j) : zero;
+#pragma unroll
+        for (int k = 0; k < SEG + 3; ++k) column(k, k < SEG + 2 ? ucol[k] : zero);
+    } else {
+        Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
+        for (int k = 0; k < S + 3; ++k) {
+            const Pt<T> u_c = u_next;
+            if (seg_on && a + k + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(a + k + 1) * nth + j);
+            column(k, u_c);
+        }
     }
 }
 

@@ -3,9 +3,9 @@
 
 namespace lwk {
 hipError_t coef_pass_f64(CoefJob &job, hipStream_t stream) { return coef_pass<double>(job, stream); }
-hipError_t step_f64(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_f64(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
-    return step_launch<double>(nt, lds, insts, items, nitems, parity, stream);
+    return step_launch<double>(nt, seg, lds, insts, items, nitems, parity, stream);
 }
 hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, const double *trig, double *cf,
                        double *ch, hipStream_t stream) {

@@ -119,17 +119,36 @@ hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
     return err;
 }
 
+// Segment lengths with a compile-time (fully unrolled) FP64 sweep
+constexpr int kFixedSeg[] = {2, 3, 4, 6, 8};
+
+template <class T, int NT>
+hipError_t step_launch_nt(int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+                          hipStream_t stream) {
+    if constexpr (words_of<T>::value == 1) {
+        switch (seg) {
+            case 2: lw_step_kernel<T, NT, 2><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
+            case 3: lw_step_kernel<T, NT, 3><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
+            case 4: lw_step_kernel<T, NT, 4><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
+            case 6: lw_step_kernel<T, NT, 6><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
+            case 8: lw_step_kernel<T, NT, 8><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
+            default: break;
+        }
+    }
+    lw_step_kernel<T, NT, 0><<<nitems, NT, lds, stream>>>(insts, items, parity);
+    return hipGetLastError();
+}
+
 template <class T>
-hipError_t step_launch(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
-                       hipStream_t stream) {
+hipError_t step_launch(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems,
+                       int parity, hipStream_t stream) {
     if (nitems <= 0) return hipSuccess;
     switch (nt) {
-        case 64: lw_step_kernel<T, 64><<<nitems, 64, lds, stream>>>(insts, items, parity); break;
-        case 128: lw_step_kernel<T, 128><<<nitems, 128, lds, stream>>>(insts, items, parity); break;
-        case 256: lw_step_kernel<T, 256><<<nitems, 256, lds, stream>>>(insts, items, parity); break;
+        case 64: return step_launch_nt<T, 64>(seg, lds, insts, items, nitems, parity, stream);
+        case 128: return step_launch_nt<T, 128>(seg, lds, insts, items, nitems, parity, stream);
+        case 256: return step_launch_nt<T, 256>(seg, lds, insts, items, nitems, parity, stream);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace lwk

@@ -3,8 +3,8 @@
 
 namespace lwk {
 hipError_t coef_pass_qd(CoefJob &job, hipStream_t stream) { return coef_pass<qd>(job, stream); }
-hipError_t step_qd(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_qd(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
-    return step_launch<qd>(nt, lds, insts, items, nitems, parity, stream);
+    return step_launch<qd>(nt, seg, lds, insts, items, nitems, parity, stream);
 }
 }  // namespace lwk

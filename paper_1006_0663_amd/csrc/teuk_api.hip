@@ -132,9 +132,9 @@ hipError_t coef_pass(int words, lwk::CoefJob &job, hipStream_t st) {
 
 hipError_t step_launch(const Batch &b, int parity) {
     switch (b.words) {
-        case 1: return lwk::step_f64(b.nt, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
-        case 2: return lwk::step_dd(b.nt, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
-        default: return lwk::step_qd(b.nt, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        case 1: return lwk::step_f64(b.nt, b.segcols, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        case 2: return lwk::step_dd(b.nt, b.segcols, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        default: return lwk::step_qd(b.nt, b.segcols, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
     }
 }
 

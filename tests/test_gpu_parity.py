@@ -37,6 +37,8 @@ def _run_gpu(w, fields, nsteps, tile=None):
 
 
 SMALL = [
+    ("flat-s0-m1", inputs.C1.with_(n_r=41, n_theta=10, rstar_min=80.0, rstar_max=130.0, s=0, m=1, a_over_M=0.0,
+                                   mass=0.0, words=2)),
     # (label, workload)  -- pulses moved inside the short domains
     ("fp64-m2", inputs.C1.with_(n_r=61, n_theta=16, rstar_min=60.0, rstar_max=150.0, words=1)),
     ("fp64-m1-a0.9", inputs.C1.with_(n_r=45, n_theta=12, rstar_min=70.0, rstar_max=140.0, m=1, a_over_M=0.9, words=1)),

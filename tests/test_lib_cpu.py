@@ -116,3 +116,24 @@ def test_host_transcendentals(W, bound):
         O = T.arith(W, 7, P, P)
         for k in range(len(xs)):
             assert abs(_val(O[k]) - mp.log(Px[k])) <= bound * max(1, abs(mp.log(Px[k]))), k
+
+
+def test_injected_allocation_failure_is_reported(monkeypatch):
+    """TEUK_FAULT=alloc makes creation fail with TEUK_ENOMEM after validation
+    and before any device call, so the error path is testable without a GPU."""
+    monkeypatch.setenv("TEUK_FAULT", "alloc")
+    for create in (lambda: T.Teuk(-2, 2, 0.5, T.make_grid(64, 16, -50, 250), 2),
+                   lambda: T.TeukBatch([(-2, 2, 0.5, T.make_grid(64, 16, -50, 250))], 4)):
+        with pytest.raises(T.TeukError) as e:
+            create()
+        assert e.value.code == T.TEUK_ENOMEM
+        assert "TEUK_FAULT" in T.lib().teuk_last_error().decode()
+
+
+def test_null_arguments_are_rejected():
+    L = T.lib()
+    assert L.teuk_step(None, 1) == T.TEUK_EINVAL
+    assert L.teuk_read_field(None, 0, None) == T.TEUK_EINVAL
+    assert L.teuk_set_launch(None, 4, 0) == T.TEUK_EINVAL
+    assert L.teuk_destroy(None) == T.TEUK_OK
+    assert L.teuk_arith_host(3, 0, None, None, None, 1) == T.TEUK_EINVAL
