@@ -38,10 +38,9 @@ def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=Non
     h.set_initial(*fields)
     if tile:
         h.set_launch(tile, 0)
-        shape = (tile, 0)
+        shape = (h.sweep, tile, 0)
     else:
-        s_, b_, _ = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)
-        shape = (s_, b_)
+        shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)[:3]
     if graph:
         h.use_graph(graph)
     h.set_initial(*fields)
@@ -138,10 +137,11 @@ def main():
         "config": {"workload": "teukolsky-lw fp64 s=-2 m=2 a/M=0.9 4096x128 r*[-200,800] cfl=%g steps=%d"
                                % (w.cfl, w.steps),
                    "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph,
-                   "segcols": shape[0], "block": shape[1]},
+                   "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1], "block": shape[2]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "lw_step_kernel<double>",
+                     "kernel": ["lw_step_kernel<double>", "lw_wide_kernel<double,run 1>",
+                                "lw_wide_kernel<double,run 2>"][shape[0]],
                      "algorithmic_bytes_per_update": bpu, "updates_per_launch": pts},
         "fp64_flops_per_update": fpu,
         "pct_fp64_peak": 100.0 * fpu * value / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
@@ -159,7 +159,8 @@ def main():
             ups = wx.n_r * wx.n_theta * wx.steps / (msx / 1e3)
             f = opcount.flops_per_update(wx.words)
             per[wx.name] = {"words": wx.words, "steps": wx.steps, "updates_per_s": ups,
-                            "ms_per_step": msx / wx.steps, "segcols": shp[0], "block": shp[1],
+                            "ms_per_step": msx / wx.steps, "sweep": ["segment", "wide", "wide2"][shp[0]],
+                            "segcols": shp[1], "block": shp[2],
                             "fp64_flops_per_update": f,
                             "pct_fp64_peak": 100.0 * f * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
                             "hbm_GBs_algorithmic": opcount.bytes_per_update(wx.words) * ups / 1e9,
@@ -185,9 +186,9 @@ def bench_batched(T, inputs, args, torch, stream, log):
         b.set_initial(k, *f)
     if args.tile:
         b.set_launch(args.tile, 0)
-        bshape = (args.tile, 0)
+        bshape = (-1, args.tile, 0)
     else:
-        bshape = autotune.tune(b, 2, [(w.n_r, w.n_theta) for w in ws], torch, stream, steps=5)[:2]
+        bshape = autotune.tune(b, 2, [(w.n_r, w.n_theta) for w in ws], torch, stream, steps=5)[:3]
     if args.graph:
         b.use_graph(args.graph)
     for k, f in enumerate(fields):
@@ -235,7 +236,7 @@ def bench_batched(T, inputs, args, torch, stream, log):
     return {"instances": len(ws), "steps": steps, "points": pts, "words": 2,
             "batched_updates_per_s": ub,
             "plain_loop_updates_per_s": pts * steps / (ms_p / 1e3),
-            "speedup": ms_p / ms_b, "segcols": bshape[0], "block": bshape[1],
+            "speedup": ms_p / ms_b, "sweep": bshape[0], "segcols": bshape[1], "block": bshape[2],
             "batched_pct_fp64_peak": 100.0 * f * ub / (FP64_VECTOR_PEAK_TFLOPS * 1e12)}
 
 

@@ -38,6 +38,12 @@
  * Argument validation happens on the host before any device work, so it needs
  * no GPU.  Calls on one handle must not overlap; different handles are
  * independent.
+ *
+ * Environment (read when a handle is created; for tests):
+ *   TEUK_FAULT=alloc      creation fails with TEUK_ENOMEM after validation;
+ *   TEUK_NO_SCALAR_ROWS   the FP64 wide sweeps stage the radial coefficient
+ *                         rows in LDS even where scalar loads could serve them
+ *                         (same results, bitwise).
  */
 #ifndef TEUK_H
 #define TEUK_H
@@ -50,6 +56,8 @@ extern "C" {
 
 typedef enum { TEUK_FP64 = 1, TEUK_DD = 2, TEUK_QD = 4 } teuk_precision; /* value = words per real */
 typedef enum { TEUK_PHI_RE = 0, TEUK_PHI_IM = 1, TEUK_PI_RE = 2, TEUK_PI_IM = 3 } teuk_field;
+/* r* sweep of the step kernel (see teuk_set_sweep) */
+enum { TEUK_SWEEP_SEGMENT = 0, TEUK_SWEEP_WIDE = 1, TEUK_SWEEP_WIDE2 = 2 };
 
 enum {
     TEUK_OK = 0,
@@ -120,10 +128,26 @@ int teuk_set_stream(teuk_t *h, void *hip_stream);
 int teuk_check_finite(teuk_t *h, int *ok);
 
 /* Launch shape of the step kernel (tuning knobs, results are unaffected):
- * segcols = r* nodes per work item (>= 1); block = threads per workgroup
- * (64, 128 or 256, at least n_theta; 0 = smallest that fits). */
+ * segcols = r* nodes per work item (>= 1); block = threads per workgroup,
+ * at least n_theta: 64, 128 or 256 for the segment sweep, up to 512 (dd)
+ * or 1024 (FP64) for the wide sweep (256 for quad-double); 0 = the default.
+ * A shape that does not fit (block too large, not enough LDS) returns
+ * TEUK_EINVAL and leaves the previous shape in place. */
 int teuk_set_tile(teuk_t *h, int segcols);
 int teuk_set_launch(teuk_t *h, int segcols, int block);
+
+/* Which r* sweep the step kernel uses (results are bitwise the same):
+ * TEUK_SWEEP_SEGMENT: each group of n_theta lanes walks its own segment of
+ *   segcols nodes, recomputing one column of overlap on each side;
+ * TEUK_SWEEP_WIDE: the groups of a block take the columns of one segment of
+ *   segcols nodes in turn and pass neighbouring values through LDS, so each
+ *   column is computed once;
+ * TEUK_SWEEP_WIDE2: the same with each lane taking two neighbouring columns
+ *   per turn (FP64 only; TEUK_ENOTSUP otherwise).
+ * -1 restores the default (wide).  Resets the
+ * block size to the default.  teuk_get_sweep returns the sweep in use. */
+int teuk_set_sweep(teuk_t *h, int sweep);
+int teuk_get_sweep(const teuk_t *h);
 
 /* Test hooks: the eight scaled coefficients at half nodes (which = 0,
  * [8][n_theta][n_r-1][p]) or nodes (which = 1, [8][n_theta][n_r][p]), or the
@@ -149,6 +173,7 @@ int teuk_batch_size(const teuk_batch_t *b);
 double teuk_batch_dt(const teuk_batch_t *b, int k);
 int teuk_batch_set_tile(teuk_batch_t *b, int segcols);
 int teuk_batch_set_launch(teuk_batch_t *b, int segcols, int block);
+int teuk_batch_set_sweep(teuk_batch_t *b, int sweep);
 /* Capture the step loop in a HIP graph of `steps_per_graph` launches (0 = off). */
 int teuk_batch_use_graph(teuk_batch_t *b, int steps_per_graph);
 int teuk_use_graph(teuk_t *h, int steps_per_graph);

@@ -1,16 +1,24 @@
 """Autotuner for the step kernel's launch shape.
 
-Times a short run of every candidate (segment length S, block size) on the
-actual instance or batch with HIP events on the handle's stream, keeps the
-fastest, and caches the choice in a JSON file keyed by device, precision and
-grid shape (``TEUK_TUNE_CACHE``, default tune_cache.json next to this file).  The
-launch shape does not change results (tested bitwise), only speed.
+Times a short run of every candidate (sweep, segment length, block size) on
+the actual instance or batch with HIP events on the handle's stream, keeps
+the fastest, and caches the choice in a JSON file keyed by device, precision
+and grid shape (``TEUK_TUNE_CACHE``, default tune_cache.json next to this
+file).  The launch shape does not change results (tested bitwise), only speed.
 """
 import json
 import os
 
-SEGCOLS = (1, 2, 3, 4, 6, 8, 12, 16)
-BLOCKS = (0, 128, 256)
+SEGMENT, WIDE, WIDE2 = 0, 1, 2
+
+# (sweep, segcols, block) per precision (words); block 0 = library default
+CANDIDATES = {
+    1: [(WIDE, s, b) for b in (128, 256, 512) for s in (4, 6, 8, 12, 16, 24)]
+       + [(WIDE2, s, b) for b in (128, 256, 512) for s in (4, 6, 8, 10, 16, 22)]
+       + [(SEGMENT, 4, 256), (SEGMENT, 8, 256)],
+    2: [(WIDE, s, b) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12)] + [(SEGMENT, 2, 0), (SEGMENT, 2, 128)],
+    4: [(WIDE, s, b) for b in (128, 256) for s in (2, 4, 6, 8, 12)] + [(SEGMENT, 2, 128), (SEGMENT, 2, 0)],
+}
 
 
 def cache_path():
@@ -40,30 +48,37 @@ def key(device_name, words, shapes):
     return "%s|w%d|%s" % (device_name, words, ";".join("%dx%d" % s for s in sorted(shapes)))
 
 
-def candidates(max_nth):
-    out = []
-    for b in BLOCKS:
-        if b and b < max_nth:
-            continue
-        for s in SEGCOLS:
-            out.append((s, b))
-    return out
+def candidates(words, max_nth):
+    return [c for c in CANDIDATES[words] if c[2] == 0 or c[2] >= max_nth]
+
+
+def apply(handle, shape):
+    sweep, segcols, block = shape
+    handle.set_sweep(sweep)
+    handle.set_launch(segcols, block)
 
 
 def tune(handle, words, shapes, torch, stream, steps=20, reps=2, use_cache=True, log=None):
-    """Pick the fastest (segcols, block) for `handle` (Teuk or TeukBatch, already
-    holding valid fields and set to `stream`).  Returns (segcols, block, us_per_step)."""
+    """Pick the fastest (sweep, segcols, block) for `handle` (Teuk or TeukBatch,
+    already holding valid fields and set to `stream`), leave the handle set to
+    it and return (sweep, segcols, block, us_per_step)."""
+    from paper_1006_0663_amd.teuk import TeukError
     dev = torch.cuda.get_device_name(0)
     k = key(dev, words, shapes)
     db = _load() if use_cache else {}
-    if k in db:
-        s, b, t = db[k]
-        handle.set_launch(s, b)
-        return s, b, t
+    if k in db and len(db[k]) == 4:
+        best = tuple(db[k])
+        apply(handle, best[:3])
+        return best
     best = None
     max_nth = max(n for _, n in shapes)
-    for s, b in candidates(max_nth):
-        handle.set_launch(s, b)
+    for cand in candidates(words, max_nth):
+        try:
+            apply(handle, cand)
+        except TeukError as ex:          # shape does not fit this device or grid
+            if log:
+                log("tune %s: %s skipped (%s)" % (k, cand, ex))
+            continue
         with torch.cuda.stream(stream):
             handle.step(2)
             times = []
@@ -76,10 +91,10 @@ def tune(handle, words, shapes, torch, stream, steps=20, reps=2, use_cache=True,
                 times.append(e0.elapsed_time(e1) * 1e3 / steps)
         t = min(times)
         if log:
-            log("tune %s: segcols=%d block=%d %.2f us/step" % (k, s, b, t))
-        if best is None or t < best[2]:
-            best = (s, b, t)
-    handle.set_launch(best[0], best[1])
+            log("tune %s: sweep=%d segcols=%d block=%d %.2f us/step" % (k, cand[0], cand[1], cand[2], t))
+        if best is None or t < best[3]:
+            best = (cand[0], cand[1], cand[2], t)
+    apply(handle, best[:3])
     if use_cache:
         db = _load()
         db[k] = list(best)

@@ -30,12 +30,28 @@ hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, cons
 
 // One step of every work item: block size nt in {64, 128, 256}.
 // seg = segment length (r* nodes per work item, as in the descriptors);
+// onfly = every instance rebuilds its coefficients per point (FP64);
 // lds = dynamic LDS bytes (radial rows of the FP64 per-point mode, else 0).
-hipError_t step_f64(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_f64(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                     hipStream_t stream);
-hipError_t step_dd(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_dd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream);
-hipError_t step_qd(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_qd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream);
+
+// One step of every work item with the wide sweep (lw_wide_kernel): block
+// size nt in {64, 128, 256, 512 (FP64, dd), 1024 (FP64, run 1)}; run = columns
+// per lane and iteration (1, or 2 for FP64); cmode = where the coefficients
+// come from: 0 stored planes, 1 radial rows staged in LDS, 2 radial rows by
+// scalar loads (n_theta a multiple of 64); one work item is one segment of the
+// descriptor's segcols nodes; lds = dynamic LDS bytes (exchange arrays plus
+// the FP64 radial rows).  attr_only: only enable `lds` bytes of dynamic LDS
+// for that kernel (needed above 64 KiB), launch nothing.
+hipError_t wide_f64(int nt, int run, int cmode, size_t lds, const InstDev *insts, const WorkItem *items, int nitems,
+                    int parity, hipStream_t stream, bool attr_only);
+hipError_t wide_dd(int nt, int run, int cmode, size_t lds, const InstDev *insts, const WorkItem *items, int nitems,
+                   int parity, hipStream_t stream, bool attr_only);
+hipError_t wide_qd(int nt, int run, int cmode, size_t lds, const InstDev *insts, const WorkItem *items, int nitems,
+                   int parity, hipStream_t stream, bool attr_only);
 
 }  // namespace lwk

@@ -78,7 +78,8 @@ MPA double rsqrt_nr(double x) {
     return y;
 }
 
-MPA void coef_fp64_point(const double *rr, double cs, double s2, double *c) {
+template <class RowPtr>
+MPA void coef_fp64_point(RowPtr rr, double cs, double s2, double *c) {
     const double X = fma(-rr[kA2D], s2, rr[kVp2]);
     const double rq = rsqrt_nr(X);
     const double q = rq * rq;
@@ -173,6 +174,26 @@ template <class T> MPA T from_words(const double *w) {
     T v;
     for (int k = 0; k < words_of<T>::value; ++k) mp_set_word(v, k, w[k]);
     return v;
+}
+
+// Device loads and stores through global-address-space pointers with 32-bit
+// offsets.  Pointers read from the descriptors are generic; without the
+// address space the compiler emits FLAT instructions, which count against
+// the LDS wait counter too, so every LDS wait would also wait for every
+// outstanding HBM load.
+#define GLB __attribute__((address_space(1)))
+#define CNS __attribute__((address_space(4)))     // constant: uniform addresses become scalar loads
+__device__ __forceinline__ const GLB double *gptr(const double *p) { return (const GLB double *)p; }
+__device__ __forceinline__ GLB double *gptr(double *p) { return (GLB double *)p; }
+template <class T> __device__ __forceinline__ T gld(const GLB double *p, uint32_t plane, uint32_t idx) {
+    T v;
+#pragma unroll
+    for (int w = 0; w < words_of<T>::value; ++w) mp_set_word(v, w, p[w * plane + idx]);
+    return v;
+}
+template <class T> __device__ __forceinline__ void gst(GLB double *p, uint32_t plane, uint32_t idx, const T &v) {
+#pragma unroll
+    for (int w = 0; w < words_of<T>::value; ++w) p[w * plane + idx] = mp_word(v, w);
 }
 
 // ------------------------------------------------------------------ coefficient pass
@@ -429,6 +450,23 @@ MPA void st_pt(double *u, size_t plane, size_t idx, const Pt<T> &p) {
     st(u + 3 * W * plane, plane, idx, p.pi.im);
 }
 
+template <class T> __device__ __forceinline__ Pt<T> gld_pt(const GLB double *u, uint32_t plane, uint32_t idx) {
+    constexpr uint32_t W = words_of<T>::value;
+    Pt<T> p;
+    p.phi.re = gld<T>(u, plane, idx);
+    p.phi.im = gld<T>(u + 1 * W * plane, plane, idx);
+    p.pi.re = gld<T>(u + 2 * W * plane, plane, idx);
+    p.pi.im = gld<T>(u + 3 * W * plane, plane, idx);
+    return p;
+}
+template <class T> __device__ __forceinline__ void gst_pt(GLB double *u, uint32_t plane, uint32_t idx, const Pt<T> &p) {
+    constexpr uint32_t W = words_of<T>::value;
+    gst(u, plane, idx, p.phi.re);
+    gst(u + 1 * W * plane, plane, idx, p.phi.im);
+    gst(u + 2 * W * plane, plane, idx, p.pi.re);
+    gst(u + 3 * W * plane, plane, idx, p.pi.im);
+}
+
 template <class T> MPA cx<T> c_avg(const cx<T> &a, const cx<T> &b) {
     return {mp_pow2(mp_add_fast(a.re, b.re), 0.5), mp_pow2(mp_add_fast(a.im, b.im), 0.5)};
 }
@@ -491,13 +529,14 @@ __device__ __forceinline__ int tap_row(int j, int k, int nth) {
 // multiword types read the weights from the table and use a rolled loop.
 template <class T>
 __device__ __forceinline__ cx<T> theta_stencil(const d2 *base, int stride, int j, int nth, int reach,
-                                               const double *__restrict__ wt, const double *w, const int *qrow) {
+                                               const GLB double *__restrict__ wt, const double *w, const int *qrow) {
     constexpr int W = words_of<T>::value;
     Acc<T> re, im;
     if constexpr (W == 1) {
 #pragma unroll
         for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
-            if (k < kMaxReach - reach || k > kMaxReach + reach) continue;
+            // taps beyond the reach carry weight 0 and row 0: adding their
+            // exact zero products costs less than branching around them
             const cx<T> x = xget<T>(base, stride, qrow[k]);
             re.prod(w[k], x.re);
             im.prod(w[k], x.im);
@@ -506,7 +545,7 @@ __device__ __forceinline__ cx<T> theta_stencil(const d2 *base, int stride, int j
 #pragma unroll 1
         for (int k = -reach; k <= reach; ++k) {
             const cx<T> x = xget<T>(base, stride, tap_row(j, k, nth));
-            const T wk = ld<T>(wt + (size_t)(k + reach) * W * nth, (size_t)nth, (size_t)j);
+            const T wk = gld<T>(wt + (uint32_t)((k + reach) * W * nth), (uint32_t)nth, (uint32_t)j);
             re.prod(wk, x.re);
             im.prod(wk, x.im);
         }
@@ -515,20 +554,17 @@ __device__ __forceinline__ cx<T> theta_stencil(const d2 *base, int stride, int j
 }
 
 // eight coefficients of node/half node i at row j: from the stored planes, or
-// (FP64 per-point mode) rebuilt from the radial row staged in LDS
-template <class T>
-__device__ __forceinline__ void load_coef(const InstDev &I, const double *planes, const double *lrow, size_t plane,
-                                          bool on, int i, int j, double cs, double s2, T *c) {
-    constexpr int W = words_of<T>::value;
-    if constexpr (W == 1) {
-        if (I.onfly) {
-            coef_fp64_point(lrow, cs, s2, c);
-            return;
-        }
-    }
-    (void)on;
+// (FP64 per-point mode, ONFLY) rebuilt from the radial row staged in LDS
+template <class T, bool ONFLY>
+__device__ __forceinline__ void load_coef(const GLB double *planes, const double *lrow, uint32_t plane, uint32_t idx,
+                                          double cs, double s2, T *c) {
+    constexpr uint32_t W = words_of<T>::value;
+    if constexpr (W == 1 && ONFLY) {
+        coef_fp64_point(lrow, cs, s2, c);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = ld<T>(planes + (size_t)q * W * plane, plane, (size_t)i * I.nth + j);
+        for (int q = 0; q < 8; ++q) c[q] = gld<T>(planes + q * W * plane, plane, idx);
+    }
 }
 
 // LDS bytes the FP64 per-point mode needs for a block of NT threads
@@ -543,8 +579,11 @@ MPA size_t rows_lds_bytes(int nt, int nth, int segcols) {
 // value at c - 3/2 (computed in iteration k-1), so each column costs one
 // barrier; then stage 2 at node c - 2 and stage 1 at half node c - 1/2.
 // Double-buffered exchange slots make one barrier per iteration sufficient.
-template <class T, int NT, int SEG>
-__global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__ insts,
+#ifndef LWK_STEP_OCC
+#define LWK_STEP_OCC
+#endif
+template <class T, int NT, int SEG, bool ONFLY>
+__global__ __launch_bounds__(NT) LWK_STEP_OCC void lw_step_kernel(const InstDev *__restrict__ insts,
                                                      const WorkItem *__restrict__ items, int parity) {
     // SEG > 0: the segment length is a compile-time constant (must equal the
     // descriptor's segcols); the sweep is then fully unrolled and every
@@ -562,9 +601,10 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     const int seg = wi.group * G + g;
     const int c0 = seg * S, c1 = min(c0 + S, nr);
     const bool seg_on = lane_on && c0 < nr;
-    const double *uin = I.u[parity];
-    double *uout = I.u[parity ^ 1];
-    const size_t plane = (size_t)nr * nth, hplane = (size_t)(nr - 1) * nth;
+    const GLB double *uin = gptr((const double *)I.u[parity]);
+    GLB double *uout = gptr(I.u[parity ^ 1]);
+    const GLB double *wtab = gptr(I.wt);
+    const uint32_t plane = (uint32_t)nr * nth, hplane = (uint32_t)(nr - 1) * nth;
     const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
     const int slot = lane_on ? g * nth + j : j;          // idle lanes never write
     const int gbase = lane_on ? g * nth : 0;
@@ -574,15 +614,13 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     const int bnB = min((wi.group * G + G) * S, nr - 1);
     double *lrow_f = lrows, *lrow_h = lrows + (size_t)(bnB - bnA + 1) * kRadRow;
     double cs_j = 0.0, s2_j = 0.0;
-    if constexpr (W == 1) {
-        if (I.onfly) {
-            const int nf = (bnB - bnA + 1) * kRadRow, nh = (bnB - bnA) * kRadRow;
-            for (int q = threadIdx.x; q < nf + nh; q += NT)
-                lrows[q] = q < nf ? I.rf[(size_t)bnA * kRadRow + q] : I.rh[(size_t)bnA * kRadRow + (q - nf)];
-            if (lane_on) {
-                cs_j = I.trig[j];
-                s2_j = I.trig[nth + j];
-            }
+    if constexpr (W == 1 && ONFLY) {
+        const int nf = (bnB - bnA + 1) * kRadRow, nh = (bnB - bnA) * kRadRow;
+        const GLB double *rf = gptr(I.rf) + bnA * kRadRow, *rh = gptr(I.rh) + bnA * kRadRow;
+        for (int q = threadIdx.x; q < nf + nh; q += NT) lrows[q] = q < nf ? rf[q] : rh[q - nf];
+        if (lane_on) {
+            cs_j = gptr(I.trig)[j];
+            s2_j = gptr(I.trig)[nth + j];
         }
     }
 
@@ -594,7 +632,7 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
             const int kk = k - kMaxReach;
             const bool tap_on = lane_on && kk >= -R && kk <= R;
-            wreg[k] = tap_on ? I.wt[(size_t)(kk + R) * nth + j] : 0.0;
+            wreg[k] = tap_on ? wtab[(uint32_t)((kk + R) * nth + j)] : 0.0;
             qrow[k] = tap_on ? tap_row(j, kk, nth) : 0;
         }
     }
@@ -602,8 +640,8 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
     // zero radial boundary nodes owned by this segment
     const Pt<T> zero = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
     if (seg_on) {
-        if (c0 == 0) st_pt(uout, plane, (size_t)j, zero);
-        if (c1 == nr) st_pt(uout, plane, (size_t)(nr - 1) * nth + j, zero);
+        if (c0 == 0) gst_pt(uout, plane, (uint32_t)j, zero);
+        if (c1 == nr) gst_pt(uout, plane, (uint32_t)((nr - 1) * nth + j), zero);
     }
     const int a = max(c0, 1) - 1;          // first node read
     const int e = min(c1, nr - 1);         // nodes a..e read; outputs a+1 .. e-1
@@ -612,31 +650,32 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         // the stages in sequence, which keeps fewer quad-double values live
         Pt<T> u_prev = zero, uh_prev = zero;
         cx<T> l_prev = zero.phi, lh_prev = zero.phi;
-        Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
+        Pt<T> u_next = (seg_on && a <= e) ? gld_pt<T>(uin, plane, (uint32_t)(a * nth + j)) : zero;
         d2 *xp = &xb[0][0][0][0], *xh = &xb[0][1][0][0];
         for (int t = 0; t < S + 2; ++t) {
             const int col = a + t;
             const Pt<T> u_cur = u_next;
-            if (seg_on && col + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(col + 1) * nth + j);
+            if (seg_on && col + 1 <= e) u_next = gld_pt<T>(uin, plane, (uint32_t)((col + 1) * nth + j));
             if (lane_on) xput<T>(xp, NT, slot, u_cur.phi);
             __syncthreads();
-            const cx<T> l_cur = theta_stencil<T>(xp + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+            const cx<T> l_cur = theta_stencil<T>(xp + gbase, NT, j, nth, R, wtab, wreg, qrow);
             // (lw1) at half node col-1/2 (index col-1)
             const bool h_on = seg_on && col <= e && t >= 1;
             T cf[8];
-            load_coef<T>(I, I.ch, nullptr, hplane, h_on, min(max(col - 1, 0), nr - 2), j, 0.0, 0.0, cf);
+            load_coef<T, false>(gptr(I.ch), nullptr, hplane, (uint32_t)(min(max(col - 1, 0), nr - 2) * nth + j), 0.0,
+                                0.0, cf);
             const Pt<T> bar = pt_avg(u_prev, u_cur);
             const Pt<T> uh_cur = lw_stage(bar, bar, pt_diff(u_prev, u_cur), c_avg(l_prev, l_cur), cf, hdt);
             if (lane_on) xput<T>(xh, NT, slot, uh_cur.phi);
             __syncthreads();
-            const cx<T> lh_cur = theta_stencil<T>(xh + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+            const cx<T> lh_cur = theta_stencil<T>(xh + gbase, NT, j, nth, R, wtab, wreg, qrow);
             if (h_on && t >= 2) {
                 // (lw2) at node col-1
                 const int i = col - 1;
-                load_coef<T>(I, I.cf, nullptr, plane, true, i, j, 0.0, 0.0, cf);
+                load_coef<T, false>(gptr(I.cf), nullptr, plane, (uint32_t)(i * nth + j), 0.0, 0.0, cf);
                 const Pt<T> un = lw_stage(u_prev, pt_avg(uh_prev, uh_cur), pt_diff(uh_prev, uh_cur),
                                           c_avg(lh_prev, lh_cur), cf, dt);
-                st_pt(uout, plane, (size_t)i * nth + j, un);
+                gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
             }
             u_prev = u_cur;
             l_prev = l_cur;
@@ -657,27 +696,27 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
             xput<T>(xh, NT, slot, uh_m32.phi);
         }
         __syncthreads();
-        const cx<T> l_c = theta_stencil<T>(xp + gbase, NT, j, nth, R, I.wt, wreg, qrow);
-        const cx<T> lh_m32 = theta_stencil<T>(xh + gbase, NT, j, nth, R, I.wt, wreg, qrow);
+        const cx<T> l_c = theta_stencil<T>(xp + gbase, NT, j, nth, R, wtab, wreg, qrow);
+        const cx<T> lh_m32 = theta_stencil<T>(xh + gbase, NT, j, nth, R, wtab, wreg, qrow);
         T cf[8];
         if (k >= 3) {
             // (lw2) at node c-2; indices are clamped so inactive lanes read valid memory
             const int i = c - 2;
             const bool on = seg_on && i <= e - 1;
             const int ic = min(max(i, 1), nr - 2);
-            load_coef<T>(I, I.cf, lrow_f + (size_t)min(max(i - bnA, 0), bnB - bnA) * kRadRow, plane, on, ic, j,
-                         cs_j, s2_j, cf);
+            load_coef<T, ONFLY>(gptr(I.cf), lrow_f + min(max(i - bnA, 0), bnB - bnA) * kRadRow, plane,
+                                (uint32_t)(ic * nth + j), cs_j, s2_j, cf);
             const Pt<T> un = lw_stage(u_m2, pt_avg(uh_m52, uh_m32), pt_diff(uh_m52, uh_m32), c_avg(lh_m52, lh_m32),
                                       cf, dt);
-            if (on) st_pt(uout, plane, (size_t)i * nth + j, un);
+            if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
         }
         Pt<T> uh_new = zero;
         if (k >= 1) {
             // (lw1) at half node c-1/2 (index c-1)
             const bool on = seg_on && c <= e;
             const int hc = min(max(c - 1, 0), nr - 2);
-            load_coef<T>(I, I.ch, lrow_h + (size_t)min(max(c - 1 - bnA, 0), bnB - bnA - 1) * kRadRow, hplane, on, hc,
-                         j, cs_j, s2_j, cf);
+            load_coef<T, ONFLY>(gptr(I.ch), lrow_h + min(max(c - 1 - bnA, 0), bnB - bnA - 1) * kRadRow, hplane,
+                                (uint32_t)(hc * nth + j), cs_j, s2_j, cf);
             const Pt<T> bar = pt_avg(u_m1, u_c);
             uh_new = lw_stage(bar, bar, pt_diff(u_m1, u_c), c_avg(l_m1, l_c), cf, hdt);
         }
@@ -692,16 +731,257 @@ __global__ __launch_bounds__(NT) void lw_step_kernel(const InstDev *__restrict__
         Pt<T> ucol[SEG + 2];
 #pragma unroll
         for (int q = 0; q < SEG + 2; ++q)
-            ucol[q] = (seg_on && a + q <= e) ? ld_pt<T>(uin, plane, (size_t)(a + q) * nth + j) : zero;
+            ucol[q] = (seg_on && a + q <= e) ? gld_pt<T>(uin, plane, (uint32_t)((a + q) * nth + j)) : zero;
 #pragma unroll
         for (int k = 0; k < SEG + 3; ++k) column(k, k < SEG + 2 ? ucol[k] : zero);
     } else {
-        Pt<T> u_next = (seg_on && a <= e) ? ld_pt<T>(uin, plane, (size_t)a * nth + j) : zero;
+        Pt<T> u_next = (seg_on && a <= e) ? gld_pt<T>(uin, plane, (uint32_t)(a * nth + j)) : zero;
         for (int k = 0; k < S + 3; ++k) {
             const Pt<T> u_c = u_next;
-            if (seg_on && a + k + 1 <= e) u_next = ld_pt<T>(uin, plane, (size_t)(a + k + 1) * nth + j);
+            if (seg_on && a + k + 1 <= e) u_next = gld_pt<T>(uin, plane, (uint32_t)((a + k + 1) * nth + j));
             column(k, u_c);
         }
+    }
+}
+
+// ------------------------------------------------------------------ wide sweep
+// The G = NT / n_theta groups of a block take the columns of one r* segment
+// in turn, each lane a run of P consecutive columns of its theta row: in
+// iteration t group g handles the run kb = tG + g, columns kb P .. kb P + P-1
+// of the nodes a..e the segment reads.  Every column of the segment is
+// computed once (only the segment's two edge columns are shared with its
+// neighbours); inside a run the left neighbour is in registers, across runs
+// it comes through LDS (u^n and L(Phi^n) for stage 1, the half step and its L
+// for stage 2).  P > 1 gives each lane independent chains to interleave.
+//
+// Exchange arrays are circular over G + 1 run slots (run kb in slot
+// kb mod (G+1)).  Phi and the half-step Phi of all P columns carry reflected
+// ghost rows (n_theta + 2 kMaxReach rows, row q at position q + kMaxReach,
+// holding the raw value of the row it mirrors: the ghost sign is in the
+// weights), so a stencil reads 2 kMaxReach + 1 consecutive rows; Pi, L(Phi)
+// and the half-step Pi and L are kept for the last column of a run only.
+// Per iteration (three barriers):
+//   put Phi^n (P columns), Pi^n of the last                  | B1
+//   stage 2 at the nodes left of each column of the previous iteration's
+//     run kb - G (its left neighbour run kb - G - 1 sits in slot
+//     (kb - G - 1) mod (G+1) == kb mod (G+1), the slot of this iteration);
+//   L(Phi^n) of the P columns, put the last; read u^n left of the run | B2
+//   read L left of the run; stage 1 at the P half nodes left of the
+//     columns; put them                                      | B3
+//   L of the half steps, put the last.
+// Slot kb mod (G+1) is next rewritten in the following iteration by group
+// g + 1 (or two iterations on by group 0); every read of a slot precedes
+// that rewrite by at least one barrier.
+MPA int wide_groups(int nt, int nth) { return nt / nth; }
+
+// LDS bytes of the exchange arrays of the wide kernel with runs of p columns
+template <class T> MPA size_t wide_xchg_bytes(int nt, int nth, int p) {
+    constexpr int CH = words_of<T>::value == 1 ? 1 : words_of<T>::value;
+    const int D = wide_groups(nt, nth) + 1, RS = nth + 2 * kMaxReach;
+    return (size_t)D * CH * sizeof(d2) * (2 * (size_t)p * RS + 4 * (size_t)nth);
+}
+// LDS bytes of the FP64 per-point radial rows of a segment of `segcols` outputs
+MPA size_t wide_rows_bytes(int segcols) { return (size_t)(2 * segcols + 3) * kRadRow * sizeof(double); }
+
+template <class T>
+__device__ __forceinline__ void xput_ghosted(d2 *slot, int rs, int j, int nth, const cx<T> &v) {
+    xput<T>(slot, rs, kMaxReach + j, v);
+    if (j < kMaxReach) xput<T>(slot, rs, kMaxReach - 1 - j, v);
+    if (j >= nth - kMaxReach) xput<T>(slot, rs, kMaxReach + 2 * nth - 1 - j, v);
+}
+
+// angular operator at row j from a ghosted slot (see theta_stencil)
+template <class T>
+__device__ __forceinline__ cx<T> stencil_ghosted(const d2 *slot, int rs, int j, int nth, int reach,
+                                                 const GLB double *__restrict__ wt, const double *w) {
+    constexpr int W = words_of<T>::value;
+    Acc<T> re, im;
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
+            const cx<T> x = xget<T>(slot, rs, j + k);      // row j + k - kMaxReach
+            re.prod(w[k], x.re);
+            im.prod(w[k], x.im);
+        }
+    } else {
+#pragma unroll 1
+        for (int k = -reach; k <= reach; ++k) {
+            const cx<T> x = xget<T>(slot, rs, kMaxReach + j + k);
+            const T wk = gld<T>(wt + (uint32_t)((k + reach) * W * nth), (uint32_t)nth, (uint32_t)j);
+            re.prod(wk, x.re);
+            im.prod(wk, x.im);
+        }
+    }
+    return {re.result(), im.result()};
+}
+
+// CM: coefficient mode -- 0 stored planes, 1 (FP64) per point from radial
+// rows staged in LDS, 2 (FP64, n_theta a multiple of the wavefront size, so
+// a wavefront lies in one group and its column is uniform) per point from
+// radial rows read with scalar loads.
+template <class T, int NT, int P, int CM>
+__global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__ insts,
+                                                     const WorkItem *__restrict__ items, int parity) {
+    constexpr int W = words_of<T>::value;
+    constexpr int CH = W == 1 ? 1 : W;
+    constexpr int RM = kMaxReach;
+    extern __shared__ d2 xs[];
+    const WorkItem wi = items[blockIdx.x];
+    const InstDev &I = insts[wi.inst];
+    const int nr = I.nr, nth = I.nth, R = I.reach, B = I.segcols;
+    const int G = wide_groups(NT, nth), D = G + 1, RS = nth + 2 * RM;
+    const int g = threadIdx.x / nth, j = threadIdx.x - g * nth;
+    const bool lane_on = g < G;
+    const int c0 = wi.group * B, c1 = min(c0 + B, nr);
+    const int a = max(c0, 1) - 1, e = min(c1, nr - 1);
+    const int K = e - a + 1;                        // columns a..e
+    const int SP = P * CH * RS;                     // doubles-pairs per ghosted slot
+    d2 *const XP = xs;                              // Phi^n        [slot][p][chunk][RS]
+    d2 *const XH = XP + D * SP;                     // half-step Phi
+    d2 *const XPI = XH + D * SP;                    // Pi^n, last column   [slot][chunk][nth]
+    d2 *const XHI = XPI + D * CH * nth;             // half-step Pi, last column
+    d2 *const XL = XHI + D * CH * nth;              // L(Phi^n), last column
+    d2 *const XLH = XL + D * CH * nth;              // L(half-step Phi), last column
+    double *const lrow_f = (double *)(XLH + D * CH * nth);    // FP64 per-point: radial rows, nodes a..e
+    double *const lrow_h = lrow_f + K * kRadRow;              //                 half nodes a..e-1
+    const GLB double *uin = gptr((const double *)I.u[parity]);
+    GLB double *uout = gptr(I.u[parity ^ 1]);
+    const GLB double *wtab = gptr(I.wt);
+    const uint32_t plane = (uint32_t)nr * nth, hplane = (uint32_t)(nr - 1) * nth;
+    const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
+    const int jj = lane_on ? j : 0;
+
+    double cs_j = 0.0, s2_j = 0.0;
+    if constexpr (W == 1 && CM == 1) {
+        const int nf = K * kRadRow, nh = (K - 1) * kRadRow;
+        const GLB double *rf = gptr(I.rf) + a * kRadRow, *rh = gptr(I.rh) + a * kRadRow;
+        for (int q = threadIdx.x; q < nf + nh; q += NT) lrow_f[q] = q < nf ? rf[q] : rh[q - nf];
+    }
+    if constexpr (W == 1 && CM > 0) {
+        cs_j = gptr(I.trig)[jj];
+        s2_j = gptr(I.trig)[nth + jj];
+    }
+    // eight coefficients at node (half = false) or half node i, row j
+    auto coef = [&](bool half, int i, T *cf) {
+        if constexpr (W == 1 && CM == 2) {
+            const int iu = __builtin_amdgcn_readfirstlane(i);
+            coef_fp64_point((const CNS double *)(half ? I.rh : I.rf) + iu * kRadRow, cs_j, s2_j, cf);
+        } else if constexpr (W == 1 && CM == 1) {
+            coef_fp64_point((half ? lrow_h : lrow_f) + (i - a) * kRadRow, cs_j, s2_j, cf);
+        } else {
+            const GLB double *pl = gptr(half ? I.ch : I.cf);
+            const uint32_t pn = half ? hplane : plane;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cf[q] = gld<T>(pl + q * W * pn, pn, (uint32_t)(i * nth + j));
+        }
+    };
+    double wreg[2 * RM + 1];
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int k = 0; k < 2 * RM + 1; ++k) {
+            const int kk = k - RM;
+            wreg[k] = (lane_on && kk >= -R && kk <= R) ? wtab[(uint32_t)((kk + R) * nth + j)] : 0.0;
+        }
+    }
+    const Pt<T> zero = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
+    if (lane_on && g == 0) {
+        if (c0 == 0) gst_pt(uout, plane, (uint32_t)j, zero);
+        if (c1 == nr) gst_pt(uout, plane, (uint32_t)((nr - 1) * nth + j), zero);
+    }
+
+    const int TI = (K + G * P - 1) / (G * P);
+    int k0 = g * P, sk = lane_on ? g : 0;           // first column of this lane's run and the run's slot
+    Pt<T> u_next[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        u_next[p] = (lane_on && k0 + p < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k0 + p) * nth + j)) : zero;
+    Pt<T> u_l[P], uh_l[P];                          // stage-2 operands kept from the previous iteration:
+    cx<T> lh_l[P];                                  // u^n left of each column, half steps, their L
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        u_l[p] = zero;
+        uh_l[p] = zero;
+        lh_l[p] = zero.phi;
+    }
+    for (int t = 0;; ++t) {
+        const int sl = sk == 0 ? G : sk - 1;        // slot of the run to the left
+        d2 *const xp = XP + sk * SP, *const xh = XH + sk * SP;
+        Pt<T> u_c[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            u_c[p] = u_next[p];
+            const int kn = k0 + G * P + p;
+            if (lane_on && kn < K) u_next[p] = gld_pt<T>(uin, plane, (uint32_t)((a + kn) * nth + j));
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (lane_on && k0 + p < K) xput_ghosted<T>(xp + p * CH * RS, RS, j, nth, u_c[p].phi);
+        const bool last_on = lane_on && k0 + P - 1 < K;
+        if (last_on) xput<T>(XPI + sk * CH * nth, nth, j, u_c[P - 1].pi);
+        __syncthreads();                                                        // B1
+        if (t >= 1 && lane_on) {
+            // stage 2 (lw2) at node a + kp - 1 for the columns kp of the previous run
+            const int k0p = k0 - G * P;
+            Pt<T> uh_m;                             // half step left of that run
+            uh_m.phi = xget<T>(xh + (P - 1) * CH * RS, RS, RM + j);
+            uh_m.pi = xget<T>(XHI + sk * CH * nth, nth, j);
+            const cx<T> lh_m = xget<T>(XLH + sk * CH * nth, nth, j);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int kp = k0p + p, i = a + kp - 1;
+                if (kp >= 2 && kp < K) {
+                    const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
+                    const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
+                    T cf[8];
+                    coef(false, i, cf);
+                    const Pt<T> un =
+                        lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
+                    gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
+                }
+            }
+        }
+        if (t == TI) break;
+        cx<T> l_c[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) l_c[p] = stencil_ghosted<T>(xp + p * CH * RS, RS, jj, nth, R, wtab, wreg);
+        if (last_on) xput<T>(XL + sk * CH * nth, nth, j, l_c[P - 1]);
+        Pt<T> u_m1;                                 // u^n left of the run
+        u_m1.phi = xget<T>(XP + sl * SP + (P - 1) * CH * RS, RS, RM + jj);
+        u_m1.pi = xget<T>(XPI + sl * CH * nth, nth, jj);
+        __syncthreads();                                                        // B2
+        Pt<T> uh[P];
+        {
+            const cx<T> l_m1 = xget<T>(XL + sl * CH * nth, nth, jj);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                // stage 1 (lw1) at half node a + k - 1/2 (half index a + k - 1)
+                const int k = k0 + p, h = a + k - 1;
+                uh[p] = zero;
+                if (lane_on && k >= 1 && k < K) {
+                    const Pt<T> &ua = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
+                    const cx<T> &la = p == 0 ? l_m1 : l_c[p > 0 ? p - 1 : 0];
+                    T cf[8];
+                    coef(true, h, cf);
+                    const Pt<T> bar = pt_avg(ua, u_c[p]);
+                    uh[p] = lw_stage(bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), cf, hdt);
+                    xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
+                }
+            }
+            if (last_on && k0 + P - 1 >= 1) xput<T>(XHI + sk * CH * nth, nth, j, uh[P - 1].pi);
+        }
+        __syncthreads();                                                        // B3
+        cx<T> lh[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) lh[p] = stencil_ghosted<T>(xh + p * CH * RS, RS, jj, nth, R, wtab, wreg);
+        if (last_on && k0 + P - 1 >= 1) xput<T>(XLH + sk * CH * nth, nth, j, lh[P - 1]);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            u_l[p] = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
+            uh_l[p] = uh[p];
+            lh_l[p] = lh[p];
+        }
+        k0 += G * P;
+        sk = sk == 0 ? G : sk - 1;                  // (kb + G) mod (G+1) == (kb - 1) mod (G+1)
     }
 }
 

@@ -3,8 +3,12 @@
 
 namespace lwk {
 hipError_t coef_pass_dd(CoefJob &job, hipStream_t stream) { return coef_pass<dd>(job, stream); }
-hipError_t step_dd(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_dd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
-    return step_launch<dd>(nt, seg, lds, insts, items, nitems, parity, stream);
+    return step_launch<dd>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);
+}
+hipError_t wide_dd(int nt, int run, int cmode, size_t lds, const InstDev *insts, const WorkItem *items,
+                    int nitems, int parity, hipStream_t stream, bool attr_only) {
+    return wide_launch<dd>(nt, run, cmode, lds, insts, items, nitems, parity, stream, attr_only);
 }
 }  // namespace lwk

@@ -3,9 +3,13 @@
 
 namespace lwk {
 hipError_t coef_pass_f64(CoefJob &job, hipStream_t stream) { return coef_pass<double>(job, stream); }
-hipError_t step_f64(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+hipError_t step_f64(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
-    return step_launch<double>(nt, seg, lds, insts, items, nitems, parity, stream);
+    return step_launch<double>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);
+}
+hipError_t wide_f64(int nt, int run, int cmode, size_t lds, const InstDev *insts, const WorkItem *items,
+                    int nitems, int parity, hipStream_t stream, bool attr_only) {
+    return wide_launch<double>(nt, run, cmode, lds, insts, items, nitems, parity, stream, attr_only);
 }
 hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, const double *trig, double *cf,
                        double *ch, hipStream_t stream) {

@@ -122,32 +122,104 @@ hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
 // Segment lengths with a compile-time (fully unrolled) FP64 sweep
 constexpr int kFixedSeg[] = {2, 3, 4, 6, 8};
 
-template <class T, int NT>
+template <class T, int NT, bool ONFLY>
 hipError_t step_launch_nt(int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                           hipStream_t stream) {
     if constexpr (words_of<T>::value == 1) {
         switch (seg) {
-            case 2: lw_step_kernel<T, NT, 2><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
-            case 3: lw_step_kernel<T, NT, 3><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
-            case 4: lw_step_kernel<T, NT, 4><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
-            case 6: lw_step_kernel<T, NT, 6><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
-            case 8: lw_step_kernel<T, NT, 8><<<nitems, NT, lds, stream>>>(insts, items, parity); return hipGetLastError();
+#define LWK_SEG(S_)                                                                                        \
+    case S_:                                                                                             \
+        lw_step_kernel<T, NT, S_, ONFLY><<<nitems, NT, lds, stream>>>(insts, items, parity);           \
+        return hipGetLastError();
+            LWK_SEG(2)
+            LWK_SEG(3)
+            LWK_SEG(4)
+            LWK_SEG(6)
+            LWK_SEG(8)
+#undef LWK_SEG
             default: break;
         }
     }
-    lw_step_kernel<T, NT, 0><<<nitems, NT, lds, stream>>>(insts, items, parity);
+    lw_step_kernel<T, NT, 0, ONFLY><<<nitems, NT, lds, stream>>>(insts, items, parity);
     return hipGetLastError();
 }
 
+// onfly: every instance of the launch rebuilds its coefficients per point (FP64 only)
 template <class T>
-hipError_t step_launch(int nt, int seg, size_t lds, const InstDev *insts, const WorkItem *items, int nitems,
-                       int parity, hipStream_t stream) {
+hipError_t step_launch(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items,
+                       int nitems, int parity, hipStream_t stream) {
     if (nitems <= 0) return hipSuccess;
+    if constexpr (words_of<T>::value == 1) {
+        if (onfly) switch (nt) {
+            case 64: return step_launch_nt<T, 64, true>(seg, lds, insts, items, nitems, parity, stream);
+            case 128: return step_launch_nt<T, 128, true>(seg, lds, insts, items, nitems, parity, stream);
+            case 256: return step_launch_nt<T, 256, true>(seg, lds, insts, items, nitems, parity, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (nt) {
-        case 64: return step_launch_nt<T, 64>(seg, lds, insts, items, nitems, parity, stream);
-        case 128: return step_launch_nt<T, 128>(seg, lds, insts, items, nitems, parity, stream);
-        case 256: return step_launch_nt<T, 256>(seg, lds, insts, items, nitems, parity, stream);
+        case 64: return step_launch_nt<T, 64, false>(seg, lds, insts, items, nitems, parity, stream);
+        case 128: return step_launch_nt<T, 128, false>(seg, lds, insts, items, nitems, parity, stream);
+        case 256: return step_launch_nt<T, 256, false>(seg, lds, insts, items, nitems, parity, stream);
         default: return hipErrorInvalidValue;
+    }
+}
+
+// ---- wide sweep (see lw_wide_kernel)
+template <class T, int NT, int P, int CM>
+hipError_t wide_launch_nt(size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+                          hipStream_t stream, bool attr_only) {
+    if (attr_only) {
+        // dynamic LDS beyond the default 64 KiB has to be enabled per kernel
+        return hipFuncSetAttribute((const void *)lw_wide_kernel<T, NT, P, CM>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    lw_wide_kernel<T, NT, P, CM><<<nitems, NT, lds, stream>>>(insts, items, parity);
+    return hipGetLastError();
+}
+
+template <class T, int P, int CM>
+hipError_t wide_launch_o(int nt, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
+                         hipStream_t stream, bool attr_only) {
+    constexpr int W = words_of<T>::value;
+    switch (nt) {
+        case 64: return wide_launch_nt<T, 64, P, CM>(lds, insts, items, nitems, parity, stream, attr_only);
+        case 128: return wide_launch_nt<T, 128, P, CM>(lds, insts, items, nitems, parity, stream, attr_only);
+        case 256: return wide_launch_nt<T, 256, P, CM>(lds, insts, items, nitems, parity, stream, attr_only);
+        case 512:
+            if constexpr (W <= 2)
+                return wide_launch_nt<T, 512, P, CM>(lds, insts, items, nitems, parity, stream, attr_only);
+            break;
+        case 1024:
+            if constexpr (W == 1 && P == 1)
+                return wide_launch_nt<T, 1024, P, CM>(lds, insts, items, nitems, parity, stream, attr_only);
+            break;
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+// run = columns per lane and iteration (1, or 2 for FP64); cmode = coefficient
+// mode of lw_wide_kernel (1 and 2 for FP64 only)
+template <class T>
+hipError_t wide_launch(int nt, int run, int cmode, size_t lds, const InstDev *insts, const WorkItem *items,
+                       int nitems, int parity, hipStream_t stream, bool attr_only) {
+    if (!attr_only && nitems <= 0) return hipSuccess;
+    if constexpr (words_of<T>::value == 1) {
+#define LWK_WIDE(P_, CM_)                                                                                     \
+    if (run == P_ && cmode == CM_)                                                                             \
+        return wide_launch_o<T, P_, CM_>(nt, lds, insts, items, nitems, parity, stream, attr_only);
+        LWK_WIDE(1, 0)
+        LWK_WIDE(1, 1)
+        LWK_WIDE(1, 2)
+        LWK_WIDE(2, 0)
+        LWK_WIDE(2, 1)
+        LWK_WIDE(2, 2)
+#undef LWK_WIDE
+        return hipErrorInvalidValue;
+    } else {
+        if (run != 1 || cmode != 0) return hipErrorInvalidValue;
+        return wide_launch_o<T, 1, 0>(nt, lds, insts, items, nitems, parity, stream, attr_only);
     }
 }
 

@@ -78,7 +78,11 @@ struct Batch {
     std::vector<Instance> inst;
     int segcols = 8;
     int nt = 64;
-    int nt_req = 0;          // requested block size (0 = smallest that fits)
+    int nt_req = 0;          // requested block size (0 = default for the sweep)
+    int sweep_req = -1;      // requested sweep (TEUK_SWEEP_*; -1 = default for the precision)
+    int sweep = 0;           // sweep in use
+    int cmode = 0;           // wide sweep: coefficient mode (see lwk::wide_launch)
+    bool no_scalar_rows = std::getenv("TEUK_NO_SCALAR_ROWS") != nullptr;   // diagnostics: force LDS rows
     size_t lds = 0;          // dynamic LDS bytes per block of the step kernel
     lwk::InstDev *d_inst = nullptr;
     lwk::WorkItem *d_items = nullptr;
@@ -130,32 +134,117 @@ hipError_t coef_pass(int words, lwk::CoefJob &job, hipStream_t st) {
     }
 }
 
+// columns per lane and iteration of a wide sweep
+int wide_run(int sweep) { return sweep == TEUK_SWEEP_WIDE2 ? 2 : 1; }
+
 hipError_t step_launch(const Batch &b, int parity) {
-    switch (b.words) {
-        case 1: return lwk::step_f64(b.nt, b.segcols, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
-        case 2: return lwk::step_dd(b.nt, b.segcols, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
-        default: return lwk::step_qd(b.nt, b.segcols, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+    bool onfly = true;
+    for (auto &I : b.inst) onfly = onfly && I.onfly;
+    if (b.words == 1 && !onfly) {
+        for (auto &I : b.inst)
+            if (I.onfly) return hipErrorInvalidValue;   // mixed modes are not produced by the API
     }
+    if (b.sweep != TEUK_SWEEP_SEGMENT) {
+        const int run = wide_run(b.sweep);
+        switch (b.words) {
+            case 1: return lwk::wide_f64(b.nt, run, b.cmode, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+            case 2: return lwk::wide_dd(b.nt, run, 0, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+            default: return lwk::wide_qd(b.nt, run, 0, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+        }
+    }
+    switch (b.words) {
+        case 1: return lwk::step_f64(b.nt, b.segcols, onfly, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        case 2: return lwk::step_dd(b.nt, b.segcols, false, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+        default: return lwk::step_qd(b.nt, b.segcols, false, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
+    }
+}
+
+int default_sweep(int words) { (void)words; return TEUK_SWEEP_WIDE; }
+int max_wide_block(int words) { return words == 1 ? 1024 : (words == 2 ? 512 : 256); }
+
+size_t wide_lds(const Batch &b, int nt) {
+    size_t need = 0;
+    for (auto &I : b.inst) {
+        size_t x = 0;
+        const int run = wide_run(b.sweep);
+        switch (b.words) {
+            case 1: x = lwk::wide_xchg_bytes<double>(nt, I.g.n_theta, run); break;
+            case 2: x = lwk::wide_xchg_bytes<lwk::dd>(nt, I.g.n_theta, run); break;
+            default: x = lwk::wide_xchg_bytes<lwk::qd>(nt, I.g.n_theta, run); break;
+        }
+        if (b.cmode == 1) x += lwk::wide_rows_bytes(b.segcols);
+        need = std::max(need, x);
+    }
+    return need;
+}
+
+int device_lds_limit() {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lim <= 0)
+        lim = 64 * 1024;
+    return lim;
 }
 
 // (Re)build descriptors and the work list; all instances must share `cur`.
 int build_worklist(Batch &b) {
     int maxnth = 0;
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
-    b.nt = maxnth <= 64 ? 64 : (maxnth <= 128 ? 128 : 256);
-    if (b.nt_req > b.nt) b.nt = b.nt_req;
-    // FP64 per-point mode stages the radial rows of a block in LDS: keep that
-    // within kMaxRowsLds by shortening the segments if needed
+    b.sweep = b.sweep_req >= 0 ? b.sweep_req : default_sweep(b.words);
     b.lds = 0;
-    for (;;) {
-        size_t need = 0;
-        for (auto &I : b.inst)
-            if (I.onfly) need = std::max(need, lwk::rows_lds_bytes(b.nt, I.g.n_theta, b.segcols));
-        if (need <= kMaxRowsLds || b.segcols == 1) {
-            b.lds = need;
-            break;
+    if (b.sweep != TEUK_SWEEP_SEGMENT) {
+        // FP64 per-point coefficients: radial rows by scalar loads when every
+        // wavefront lies in one theta column (n_theta a multiple of 64), else
+        // staged in LDS
+        bool onfly = b.words == 1, wave_cols = true;
+        for (auto &I : b.inst) {
+            onfly = onfly && I.onfly;
+            wave_cols = wave_cols && I.g.n_theta % 64 == 0;
         }
-        b.segcols -= 1;
+        b.cmode = !onfly ? 0 : (wave_cols && !b.no_scalar_rows ? 2 : 1);
+        // FP64 radial rows of a segment stay within kMaxRowsLds
+        while (b.segcols > 1 && lwk::wide_rows_bytes(b.segcols) > kMaxRowsLds) b.segcols -= 1;
+        const size_t lim = (size_t)device_lds_limit();
+        if (b.nt_req) {
+            if (b.nt_req > max_wide_block(b.words)) return fail(TEUK_EINVAL, "block too large for this precision");
+            b.nt = b.nt_req;
+            b.lds = wide_lds(b, b.nt);
+            if (b.lds > lim) return fail(TEUK_EINVAL, "launch shape needs more LDS than the device has");
+        } else {
+            // about four theta columns per block, fewer if LDS runs short (the
+            // default shape stays within the 64 KiB every launch gets)
+            const size_t cap = std::min<size_t>(lim, 64 * 1024);
+            int nt = 64;
+            while (nt < 4 * maxnth && nt < max_wide_block(b.words)) nt *= 2;
+            while (nt / 2 >= maxnth && wide_lds(b, nt) > cap) nt /= 2;
+            b.nt = nt;
+            b.lds = wide_lds(b, nt);
+            if (b.lds > lim) return fail(TEUK_EINVAL, "n_theta too large for the device's LDS");
+        }
+        if (b.lds > 64 * 1024) {
+            const int run = wide_run(b.sweep);
+            hipError_t e =
+                b.words == 1 ? lwk::wide_f64(b.nt, run, b.cmode, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
+                : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
+                               : lwk::wide_qd(b.nt, run, 0, b.lds, nullptr, nullptr, 0, 0, nullptr, true);
+            if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(dynamic LDS)");
+        }
+    } else {
+        b.nt = maxnth <= 64 ? 64 : (maxnth <= 128 ? 128 : 256);
+        if (b.nt_req > b.nt) b.nt = b.nt_req;
+        if (b.nt > 256) return fail(TEUK_EINVAL, "the segment sweep takes blocks of at most 256 threads");
+        // FP64 per-point mode stages the radial rows of a block in LDS: keep that
+        // within kMaxRowsLds by shortening the segments if needed
+        for (;;) {
+            size_t need = 0;
+            for (auto &I : b.inst)
+                if (I.onfly) need = std::max(need, lwk::rows_lds_bytes(b.nt, I.g.n_theta, b.segcols));
+            if (need <= kMaxRowsLds || b.segcols == 1) {
+                b.lds = need;
+                break;
+            }
+            b.segcols -= 1;
+        }
     }
     std::vector<lwk::InstDev> hd(b.inst.size());
     std::vector<lwk::WorkItem> items;
@@ -172,7 +261,7 @@ int build_worklist(Batch &b) {
         D.nth = I.g.n_theta;
         D.reach = I.reach;
         D.segcols = b.segcols;
-        const int G = b.nt / D.nth;
+        const int G = b.sweep != TEUK_SWEEP_SEGMENT ? 1 : b.nt / D.nth;   // wide: one segment per block
         const int nseg = (D.nr + b.segcols - 1) / b.segcols;
         D.groups = (nseg + G - 1) / G;
         D.words = I.words;
@@ -483,17 +572,58 @@ int teuk_set_tile(teuk_t *h, int segcols) {
 }
 
 static int set_launch(Batch &b, int segcols, int block) {
-    if (segcols < 1 || (block != 0 && block != 64 && block != 128 && block != 256))
-        return fail(TEUK_EINVAL, "segcols must be >= 1 and block one of 0, 64, 128, 256");
+    if (segcols < 1 || (block != 0 && block != 64 && block != 128 && block != 256 && block != 512 && block != 1024))
+        return fail(TEUK_EINVAL, "segcols must be >= 1 and block one of 0, 64, 128, 256, 512, 1024");
     int maxnth = 0;
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     if (block != 0 && block < maxnth) return fail(TEUK_EINVAL, "block must be >= n_theta");
     if (int rc = check_ok(b)) return rc;
     hipStreamSynchronize(b.stream);
+    const int old_seg = b.segcols, old_nt = b.nt_req;
     b.segcols = segcols;
     b.nt_req = block;
-    return build_worklist(b);
+    int rc = build_worklist(b);
+    if (rc != TEUK_OK) {
+        // keep the handle usable with its previous shape
+        b.segcols = old_seg;
+        b.nt_req = old_nt;
+        const std::string msg = g_err;
+        build_worklist(b);
+        return fail(rc, msg);
+    }
+    return TEUK_OK;
 }
+
+static int set_sweep(Batch &b, int sweep) {
+    if (sweep != -1 && sweep != TEUK_SWEEP_SEGMENT && sweep != TEUK_SWEEP_WIDE && sweep != TEUK_SWEEP_WIDE2)
+        return fail(TEUK_EINVAL, "sweep must be -1 (default), 0 (segment), 1 (wide) or 2 (wide, runs of two)");
+    if (sweep == TEUK_SWEEP_WIDE2 && b.words != 1)
+        return fail(TEUK_ENOTSUP, "the wide sweep with runs of two columns is built for FP64 only");
+    if (int rc = check_ok(b)) return rc;
+    hipStreamSynchronize(b.stream);
+    const int old = b.sweep_req, old_nt = b.nt_req;
+    b.sweep_req = sweep;
+    b.nt_req = 0;
+    int rc = build_worklist(b);
+    if (rc != TEUK_OK) {
+        b.sweep_req = old;
+        b.nt_req = old_nt;
+        const std::string msg = g_err;
+        build_worklist(b);
+        return fail(rc, msg);
+    }
+    return TEUK_OK;
+}
+
+int teuk_set_sweep(teuk_t *h, int sweep) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_sweep(h->b, sweep);
+}
+int teuk_batch_set_sweep(teuk_batch_t *b, int sweep) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_sweep(b->b, sweep);
+}
+int teuk_get_sweep(const teuk_t *h) { return h ? h->b.sweep : TEUK_EINVAL; }
 
 int teuk_set_launch(teuk_t *h, int segcols, int block) {
     if (!h) return fail(TEUK_EINVAL, "handle is NULL");

@@ -1,8 +1,10 @@
 """Profiling driver: run a fixed number of steps of one workload with a fixed
-launch shape, after a device-to-device copy of known size that calibrates
-byte counters (run it under rocprofv3).
+launch shape (or the autotuner's, from its cache when present), after a
+device-to-device copy of known size that calibrates byte counters (run it
+under rocprofv3).
 
-    python -m paper_1006_0663_amd.profile_step --workload fp64-4096x128 --steps 50 --segcols 4 --block 256
+    python -m paper_1006_0663_amd.profile_step --workload fp64-4096x128 --steps 50 --sweep 1 --segcols 16 --block 512
+    python -m paper_1006_0663_amd.profile_step --workload fp64-4096x128 --steps 50 --tuned
 """
 import argparse
 import sys
@@ -20,6 +22,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--segcols", type=int, default=4)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--sweep", type=int, default=-1, help="0 segment, 1 wide, 2 wide with runs of two, -1 default")
+    ap.add_argument("--tuned", action="store_true", help="use the autotuner's shape (cached if tuned before)")
     a = ap.parse_args()
     w = inputs.WORKLOADS[a.workload]
     torch.cuda.set_device(0)
@@ -29,13 +33,21 @@ def main():
     torch.cuda.synchronize()
     g = T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
     h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
-    h.set_launch(a.segcols, a.block)
     h.set_initial(*inputs.initial_fields(w))
+    if a.tuned:
+        from paper_1006_0663_amd import autotune
+        stream = torch.cuda.current_stream()
+        h.set_stream(stream.cuda_stream)
+        a.sweep, a.segcols, a.block, _ = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)
+        h.set_initial(*inputs.initial_fields(w))
+    else:
+        h.set_sweep(a.sweep)
+        h.set_launch(a.segcols, a.block)
     h.step(a.steps)
     ok = h.check_finite()
     h.close()
-    print("profile_step: %s %d steps segcols=%d block=%d finite=%s copy=%d MiB"
-          % (w.name, a.steps, a.segcols, a.block, ok, COPY_MIB), flush=True)
+    print("profile_step: %s %d steps sweep=%d segcols=%d block=%d finite=%s copy=%d MiB"
+          % (w.name, a.steps, a.sweep, a.segcols, a.block, ok, COPY_MIB), flush=True)
     return 0 if ok else 1
 
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libteuk.so")
 
 TEUK_OK, TEUK_EINVAL, TEUK_ENOMEM, TEUK_EDEVICE, TEUK_ENOTSUP, TEUK_ENONFINITE = 0, -1, -2, -3, -4, -5
 FP64, DD, QD = 1, 2, 4
+SWEEP_SEGMENT, SWEEP_WIDE, SWEEP_WIDE2 = 0, 1, 2
 PHI_RE, PHI_IM, PI_RE, PI_IM = 0, 1, 2, 3
 
 
@@ -54,6 +55,9 @@ _SIGS = {
     "teuk_set_tile": ([_P, ctypes.c_int], ctypes.c_int),
     "teuk_set_launch": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "teuk_batch_set_launch": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "teuk_set_sweep": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_get_sweep": ([_P], ctypes.c_int),
+    "teuk_batch_set_sweep": ([_P, ctypes.c_int], ctypes.c_int),
     "teuk_get_coefficients": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "teuk_set_coefficients": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "teuk_batch_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _D,
@@ -170,6 +174,13 @@ class Teuk:
     def use_graph(self, k):
         _check(lib().teuk_use_graph(self.h, int(k)))
 
+    def set_sweep(self, sweep):
+        _check(lib().teuk_set_sweep(self.h, int(sweep)))
+
+    @property
+    def sweep(self):
+        return lib().teuk_get_sweep(self.h)
+
     def check_finite(self):
         ok = ctypes.c_int(0)
         rc = lib().teuk_check_finite(self.h, ctypes.byref(ok))
@@ -245,6 +256,9 @@ class TeukBatch:
 
     def set_launch(self, segcols, block=0):
         _check(lib().teuk_batch_set_launch(self.h, int(segcols), int(block)))
+
+    def set_sweep(self, sweep):
+        _check(lib().teuk_batch_set_sweep(self.h, int(sweep)))
 
     def use_graph(self, k):
         _check(lib().teuk_batch_use_graph(self.h, int(k)))

@@ -25,10 +25,12 @@ def _grid(w):
     return T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
 
 
-def _run_gpu(w, fields, nsteps, tile=None):
+def _run_gpu(w, fields, nsteps, tile=None, sweep=None, block=0):
     h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), w.words)
+    if sweep is not None:
+        h.set_sweep(sweep)
     if tile:
-        h.set_tile(tile)
+        h.set_launch(tile, block)
     h.set_initial(*fields)
     h.step(nsteps)
     out = h.fields()
@@ -50,12 +52,15 @@ SMALL = [
 ]
 
 
+@pytest.mark.parametrize("sweep", [T.SWEEP_SEGMENT, T.SWEEP_WIDE, T.SWEEP_WIDE2], ids=["segment", "wide", "wide2"])
 @pytest.mark.parametrize("label,w", SMALL, ids=[x[0] for x in SMALL])
-def test_small_grid_parity(label, w):
+def test_small_grid_parity(label, w, sweep):
+    if sweep == T.SWEEP_WIDE2 and w.words != 1:
+        pytest.skip("runs of two columns are built for FP64 only")
     nsteps = 24
     fields = inputs.initial_fields(w)
-    _note("parity %s: %dx%d words=%d steps=%d" % (label, w.n_r, w.n_theta, w.words, nsteps))
-    got = _run_gpu(w, fields, nsteps, tile=8)
+    _note("parity %s sweep %d: %dx%d words=%d steps=%d" % (label, sweep, w.n_r, w.n_theta, w.words, nsteps))
+    got = _run_gpu(w, fields, nsteps, tile=8, sweep=sweep)
     ref = oracle_run(w, fields, nsteps)
     err = rel_linf(got, ref)
     _note("  rel Linf = %.3e (tolerance %.0e)" % (err, TOL[w.words]))
@@ -108,6 +113,79 @@ def test_batched_equals_single_bitwise():
     b.step(15)
     for k, w in enumerate(ws):
         single = _run_gpu(w, fields[k], 15, tile=6)
+        for f in range(4):
+            assert np.array_equal(b.read_field(k, f), single[f]), (k, f)
+    b.close()
+
+
+# launch shapes: (sweep, segcols, block); the wide sweep with several theta
+# groups per block, one group per block, segments of one node, ragged tails
+SHAPES = [(T.SWEEP_SEGMENT, 8, 0), (T.SWEEP_SEGMENT, 3, 64), (T.SWEEP_WIDE, 8, 0), (T.SWEEP_WIDE, 1, 0),
+          (T.SWEEP_WIDE, 5, 64), (T.SWEEP_WIDE, 13, 256), (T.SWEEP_WIDE, 40, 0), (T.SWEEP_WIDE2, 8, 0),
+          (T.SWEEP_WIDE2, 1, 0), (T.SWEEP_WIDE2, 5, 64), (T.SWEEP_WIDE2, 11, 128), (T.SWEEP_WIDE2, 40, 512)]
+
+
+@pytest.mark.parametrize("words", [1, 2, 4])
+def test_sweeps_and_launch_shapes_are_bitwise(words):
+    """Every sweep and launch shape gives the same bits (they run the same
+    per-point arithmetic in the same order), also when the segment length does
+    not divide n_r and n_theta does not divide the block."""
+    w = inputs.C1.with_(n_r=53, n_theta=24, rstar_min=60.0, rstar_max=150.0, words=words, m=1, a_over_M=0.7)
+    fields = inputs.initial_fields(w)
+    ref = None
+    for sweep, seg, block in SHAPES:
+        if (words == 4 and block > 256) or (sweep == T.SWEEP_WIDE2 and words != 1):
+            continue
+        _note("shape words=%d sweep=%d segcols=%d block=%d" % (words, sweep, seg, block))
+        got = _run_gpu(w, fields, 9, tile=seg, sweep=sweep, block=block)
+        if ref is None:
+            ref = got
+            assert rel_linf(got, oracle_run(w, fields, 9)) <= TOL[words]
+        for f in range(4):
+            assert np.array_equal(got[f], ref[f]), (sweep, seg, block, f)
+
+
+@pytest.mark.parametrize("sweep", [T.SWEEP_WIDE, T.SWEEP_WIDE2], ids=["wide", "wide2"])
+def test_fp64_coefficient_row_modes_are_bitwise(sweep, monkeypatch):
+    """n_theta a multiple of 64: the FP64 wide sweeps read the radial rows with
+    scalar loads; TEUK_NO_SCALAR_ROWS stages them in LDS instead.  Same bits,
+    and both match the oracle."""
+    w = inputs.C1.with_(n_r=45, n_theta=64, rstar_min=60.0, rstar_max=150.0, words=1, m=2, a_over_M=0.9)
+    fields = inputs.initial_fields(w)
+    _note("row modes sweep %d" % sweep)
+    got = _run_gpu(w, fields, 8, tile=9, sweep=sweep, block=128)
+    monkeypatch.setenv("TEUK_NO_SCALAR_ROWS", "1")
+    lds_rows = _run_gpu(w, fields, 8, tile=9, sweep=sweep, block=128)
+    for f in range(4):
+        assert np.array_equal(got[f], lds_rows[f]), f
+    assert rel_linf(got, oracle_run(w, fields, 8)) <= TOL[1]
+
+
+def test_wide2_rejected_for_multiword():
+    w = inputs.C1.with_(n_r=20, n_theta=8, words=2)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 2)
+    with pytest.raises(T.TeukError) as ex:
+        h.set_sweep(T.SWEEP_WIDE2)
+    assert ex.value.code == T.TEUK_ENOTSUP
+    assert h.sweep == T.SWEEP_WIDE
+    h.close()
+
+
+@pytest.mark.parametrize("sweep", [T.SWEEP_WIDE, T.SWEEP_WIDE2], ids=["wide", "wide2"])
+def test_wide_sweep_batch_equals_single(sweep):
+    ws = [inputs.C1.with_(n_r=40 + 9 * k, n_theta=nth, rstar_min=60.0, rstar_max=150.0, m=k % 3,
+                          a_over_M=0.25 * k, words=1, seed=k)
+          for k, nth in enumerate((8, 40, 16, 64))]
+    _note("wide batched vs single, %d instances, sweep %d" % (len(ws), sweep))
+    b = T.TeukBatch([(w.s, w.m, w.a_over_M, _grid(w)) for w in ws], 1)
+    b.set_sweep(sweep)
+    b.set_launch(7, 0)
+    fields = [inputs.initial_fields(w) for w in ws]
+    for k, f in enumerate(fields):
+        b.set_initial(k, *f)
+    b.step(11)
+    for k, w in enumerate(ws):
+        single = _run_gpu(w, fields[k], 11, tile=7, sweep=sweep)
         for f in range(4):
             assert np.array_equal(b.read_field(k, f), single[f]), (k, f)
     b.close()
