@@ -819,7 +819,8 @@ __device__ __forceinline__ cx<T> stencil_ghosted(const d2 *slot, int rs, int j, 
 // rows staged in LDS, 2 (FP64, n_theta a multiple of the wavefront size, so
 // a wavefront lies in one group and its column is uniform) per point from
 // radial rows read with scalar loads.
-template <class T, int NT, int P, int CM>
+// TM > 0: at most TM iterations (the host checks), all loads issued up front.
+template <class T, int NT, int P, int CM, int TM>
 __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__ insts,
                                                      const WorkItem *__restrict__ items, int parity) {
     constexpr int W = words_of<T>::value;
@@ -872,7 +873,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
             const GLB double *pl = gptr(half ? I.ch : I.cf);
             const uint32_t pn = half ? hplane : plane;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) cf[q] = gld<T>(pl + q * W * pn, pn, (uint32_t)(i * nth + j));
+            for (int q = 0; q < 8; ++q) cf[q] = gld<T>(pl + q * W * pn, pn, (uint32_t)(i * nth + jj));
         }
     };
     double wreg[2 * RM + 1];
@@ -889,12 +890,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
         if (c1 == nr) gst_pt(uout, plane, (uint32_t)((nr - 1) * nth + j), zero);
     }
 
-    const int TI = (K + G * P - 1) / (G * P);
+    const int TI = (K + G * P - 1) / (G * P);       // iterations with columns (TM >= TI when TM > 0)
     int k0 = g * P, sk = lane_on ? g : 0;           // first column of this lane's run and the run's slot
-    Pt<T> u_next[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-        u_next[p] = (lane_on && k0 + p < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k0 + p) * nth + j)) : zero;
     Pt<T> u_l[P], uh_l[P];                          // stage-2 operands kept from the previous iteration:
     cx<T> lh_l[P];                                  // u^n left of each column, half steps, their L
 #pragma unroll
@@ -903,44 +900,40 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
         uh_l[p] = zero;
         lh_l[p] = zero.phi;
     }
-    for (int t = 0;; ++t) {
+    // iteration t on the run's columns u_c; false once the last stage 2 is done
+    auto iteration = [&](int t, const Pt<T> *u_c) -> bool {
         const int sl = sk == 0 ? G : sk - 1;        // slot of the run to the left
         d2 *const xp = XP + sk * SP, *const xh = XH + sk * SP;
-        Pt<T> u_c[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            u_c[p] = u_next[p];
-            const int kn = k0 + G * P + p;
-            if (lane_on && kn < K) u_next[p] = gld_pt<T>(uin, plane, (uint32_t)((a + kn) * nth + j));
-        }
 #pragma unroll
         for (int p = 0; p < P; ++p)
             if (lane_on && k0 + p < K) xput_ghosted<T>(xp + p * CH * RS, RS, j, nth, u_c[p].phi);
         const bool last_on = lane_on && k0 + P - 1 < K;
         if (last_on) xput<T>(XPI + sk * CH * nth, nth, j, u_c[P - 1].pi);
         __syncthreads();                                                        // B1
-        if (t >= 1 && lane_on) {
+        // Stages run on every lane with clamped indices (results of idle lanes
+        // and of columns outside the segment are discarded); only the stores
+        // are conditional, which keeps each phase one basic block.
+        if (t >= 1) {
             // stage 2 (lw2) at node a + kp - 1 for the columns kp of the previous run
             const int k0p = k0 - G * P;
             Pt<T> uh_m;                             // half step left of that run
-            uh_m.phi = xget<T>(xh + (P - 1) * CH * RS, RS, RM + j);
-            uh_m.pi = xget<T>(XHI + sk * CH * nth, nth, j);
-            const cx<T> lh_m = xget<T>(XLH + sk * CH * nth, nth, j);
+            uh_m.phi = xget<T>(xh + (P - 1) * CH * RS, RS, RM + jj);
+            uh_m.pi = xget<T>(XHI + sk * CH * nth, nth, jj);
+            const cx<T> lh_m = xget<T>(XLH + sk * CH * nth, nth, jj);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int kp = k0p + p, i = a + kp - 1;
-                if (kp >= 2 && kp < K) {
-                    const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
-                    const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
-                    T cf[8];
-                    coef(false, i, cf);
-                    const Pt<T> un =
-                        lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
-                    gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
-                }
+                const int ic = min(max(i, a), e);
+                const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
+                const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
+                T cf[8];
+                coef(false, ic, cf);
+                const Pt<T> un =
+                    lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
+                if (lane_on && kp >= 2 && kp < K) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
             }
         }
-        if (t == TI) break;
+        if (t == TI) return false;
         cx<T> l_c[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) l_c[p] = stencil_ghosted<T>(xp + p * CH * RS, RS, jj, nth, R, wtab, wreg);
@@ -956,16 +949,14 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
             for (int p = 0; p < P; ++p) {
                 // stage 1 (lw1) at half node a + k - 1/2 (half index a + k - 1)
                 const int k = k0 + p, h = a + k - 1;
-                uh[p] = zero;
-                if (lane_on && k >= 1 && k < K) {
-                    const Pt<T> &ua = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
-                    const cx<T> &la = p == 0 ? l_m1 : l_c[p > 0 ? p - 1 : 0];
-                    T cf[8];
-                    coef(true, h, cf);
-                    const Pt<T> bar = pt_avg(ua, u_c[p]);
-                    uh[p] = lw_stage(bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), cf, hdt);
-                    xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
-                }
+                const int hc = min(max(h, a), e - 1);
+                const Pt<T> &ua = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
+                const cx<T> &la = p == 0 ? l_m1 : l_c[p > 0 ? p - 1 : 0];
+                T cf[8];
+                coef(true, hc, cf);
+                const Pt<T> bar = pt_avg(ua, u_c[p]);
+                uh[p] = lw_stage(bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), cf, hdt);
+                if (lane_on && k >= 1 && k < K) xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
             }
             if (last_on && k0 + P - 1 >= 1) xput<T>(XHI + sk * CH * nth, nth, j, uh[P - 1].pi);
         }
@@ -982,6 +973,37 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
         }
         k0 += G * P;
         sk = sk == 0 ? G : sk - 1;                  // (kb + G) mod (G+1) == (kb - 1) mod (G+1)
+        return true;
+    };
+    if constexpr (TM > 0) {
+        // every column of the lane requested up front: one memory latency per
+        // launch instead of one per iteration
+        Pt<T> ua[TM][P];
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int k = k0 + t * G * P + p;
+                ua[t][p] = (lane_on && t < TI && k < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k) * nth + j)) : zero;
+            }
+#pragma unroll
+        for (int t = 0; t <= TM; ++t)
+            if (!iteration(t, ua[t < TM ? t : TM - 1])) break;
+    } else {
+        Pt<T> u_next[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            u_next[p] = (lane_on && k0 + p < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k0 + p) * nth + j)) : zero;
+        for (int t = 0;; ++t) {
+            Pt<T> u_c[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                u_c[p] = u_next[p];
+                const int kn = k0 + G * P + p;
+                if (lane_on && kn < K) u_next[p] = gld_pt<T>(uin, plane, (uint32_t)((a + kn) * nth + j));
+            }
+            if (!iteration(t, u_c)) break;
+        }
     }
 }
 

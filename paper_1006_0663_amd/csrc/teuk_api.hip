@@ -82,6 +82,7 @@ struct Batch {
     int sweep_req = -1;      // requested sweep (TEUK_SWEEP_*; -1 = default for the precision)
     int sweep = 0;           // sweep in use
     int cmode = 0;           // wide sweep: coefficient mode (see lwk::wide_launch)
+    int tm = 0;              // wide sweep: unrolled iteration count (0 = loop)
     bool no_scalar_rows = std::getenv("TEUK_NO_SCALAR_ROWS") != nullptr;   // diagnostics: force LDS rows
     size_t lds = 0;          // dynamic LDS bytes per block of the step kernel
     lwk::InstDev *d_inst = nullptr;
@@ -147,9 +148,13 @@ hipError_t step_launch(const Batch &b, int parity) {
     if (b.sweep != TEUK_SWEEP_SEGMENT) {
         const int run = wide_run(b.sweep);
         switch (b.words) {
-            case 1: return lwk::wide_f64(b.nt, run, b.cmode, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
-            case 2: return lwk::wide_dd(b.nt, run, 0, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
-            default: return lwk::wide_qd(b.nt, run, 0, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+            case 1:
+                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream,
+                                     false);
+            case 2:
+                return lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+            default:
+                return lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
         }
     }
     switch (b.words) {
@@ -184,6 +189,27 @@ int device_lds_limit() {
         lim <= 0)
         lim = 64 * 1024;
     return lim;
+}
+
+// XCD-aware order of one instance's work items (positions first..first+n-1
+// of the list, i.e. blocks first.. of the launch).  The GPU hands block b to
+// XCD b mod kXcds; the blocks one XCD receives get consecutive segments, so a
+// column two neighbouring segments both read is fetched through one L2.
+constexpr int kXcds = 8;
+void xcd_order(std::vector<lwk::WorkItem> &items, size_t first, size_t n) {
+    const std::vector<lwk::WorkItem> src(items.begin() + first, items.begin() + first + n);
+    size_t cnt[kXcds] = {}, base[kXcds] = {}, seen[kXcds] = {};
+    for (size_t l = 0; l < n; ++l) cnt[(first + l) % kXcds]++;
+    size_t acc = 0;
+    for (int q = 0; q < kXcds; ++q) {
+        const size_t x = (first + q) % kXcds;
+        base[x] = acc;
+        acc += cnt[x];
+    }
+    for (size_t l = 0; l < n; ++l) {
+        const size_t x = (first + l) % kXcds;
+        items[first + l] = src[base[x] + seen[x]++];
+    }
 }
 
 // (Re)build descriptors and the work list; all instances must share `cur`.
@@ -221,12 +247,19 @@ int build_worklist(Batch &b) {
             b.lds = wide_lds(b, nt);
             if (b.lds > lim) return fail(TEUK_EINVAL, "n_theta too large for the device's LDS");
         }
+        // iterations a work item needs: its columns over the columns a block takes per iteration
+        int ti = 0;
+        for (auto &I : b.inst) {
+            const int K = std::min(b.segcols, I.g.n_r) + 2, per = (b.nt / I.g.n_theta) * wide_run(b.sweep);
+            ti = std::max(ti, (K + per - 1) / per);
+        }
+        b.tm = ti <= 2 ? 2 : (ti <= 4 ? ti : 0);
         if (b.lds > 64 * 1024) {
             const int run = wide_run(b.sweep);
             hipError_t e =
-                b.words == 1 ? lwk::wide_f64(b.nt, run, b.cmode, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
-                : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
-                               : lwk::wide_qd(b.nt, run, 0, b.lds, nullptr, nullptr, 0, 0, nullptr, true);
+                b.words == 1 ? lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
+                : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
+                               : lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, nullptr, nullptr, 0, 0, nullptr, true);
             if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(dynamic LDS)");
         }
     } else {
@@ -277,8 +310,11 @@ int build_worklist(Batch &b) {
         std::memcpy(D.hdt, I.hdt, sizeof D.hdt);
         std::memcpy(D.dt, I.dt, sizeof D.dt);
     }
-    for (int k : order)
+    for (int k : order) {
+        const size_t first = items.size();
         for (int gi = 0; gi < hd[k].groups; ++gi) items.push_back({k, gi});
+        xcd_order(items, first, items.size() - first);
+    }
     hipFree(b.d_inst);
     hipFree(b.d_items);
     b.d_inst = nullptr;
