@@ -22,6 +22,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
+# HBM bytes per launch of the headline kernel, from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE runs of paper_1006_0663_amd/profile_step.py (the summary under
+# profiles/ gives the commands).  FETCH_SIZE reads 131,093 KiB for a 256 MiB
+# device copy (scale 2.0), WRITE_SIZE 262,144 KiB (scale 1.0).  Valid only for
+# the launch shape and kernel sources they were taken with: `source` is
+# kernel_source_digest() at that time; otherwise traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "shape": (2, 4, 128), "source": "909148a8630a",
+    "fetch_kib": 9425.4, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0,
+}
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("kernels.hpp", "mparith.hpp", "mpdot.hpp"):
+        with open(os.path.join(ROOT, "paper_1006_0663_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
 
 def _torch():
     import torch
@@ -30,13 +50,16 @@ def _torch():
     return torch
 
 
-def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=None):
+def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=None, fixed_shape=None):
     from paper_1006_0663_amd import autotune
     g = T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
     h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
     h.set_stream(stream.cuda_stream)
     h.set_initial(*fields)
-    if tile:
+    if fixed_shape:
+        autotune.apply(h, fixed_shape)
+        shape = tuple(fixed_shape)
+    elif tile:
         h.set_launch(tile, 0)
         shape = (h.sweep, tile, 0)
     else:
@@ -99,6 +122,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--graph", type=int, default=100, help="steps per captured HIP graph (0 = plain launches)")
     ap.add_argument("--tile", type=int, default=0, help="r* nodes per segment (0 = library default)")
+    ap.add_argument("--shape", default="", help="headline launch shape 'sweep,segcols,block' (default: autotuned)")
     ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=32)
@@ -121,14 +145,20 @@ def main():
     log("bench: generating %s inputs" % w.name)
     fields = inputs.initial_fields(w)
     log("bench: timing %s, %d warmup + %d steps" % (w.name, args.warmup, args.steps))
+    fixed = tuple(int(x) for x in args.shape.split(",")) if args.shape else None
     ms, wall, finite, shape = time_single(T, w, fields, args.steps, args.warmup, args.graph, args.tile, torch,
-                                          stream, log)
+                                          stream, log, fixed)
     pts = w.n_r * w.n_theta
     value = pts * args.steps / (ms / 1e3)
     ms_step = ms / args.steps
     bpu = opcount.bytes_per_update(1)
     achieved = bpu * pts / (ms_step / 1e3) / 1e9
     fpu = opcount.flops_per_update(1)
+    traffic = traffic_bytes = None
+    m = MEASURED_TRAFFIC
+    if tuple(shape) == m["shape"] and kernel_source_digest() == m["source"]:
+        traffic_bytes = 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+        traffic = traffic_bytes / (ms_step / 1e3) / 1e9
     out = {
         "metric": "grid-point updates/sec per precision (FP64/dd/qd) + % FP64 peak; batched vs plain",
         "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
@@ -139,7 +169,8 @@ def main():
                    "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph,
                    "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1], "block": shape[2]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": ["lw_step_kernel<double>", "lw_wide_kernel<double,run 1>",
                                 "lw_wide_kernel<double,run 2>"][shape[0]],
                      "algorithmic_bytes_per_update": bpu, "updates_per_launch": pts},

@@ -54,6 +54,7 @@ def candidates(words, max_nth):
 
 def apply(handle, shape):
     sweep, segcols, block = shape
+    handle.set_launch(1, 0)          # a shape every sweep accepts
     handle.set_sweep(sweep)
     handle.set_launch(segcols, block)
 

@@ -744,6 +744,14 @@ __global__ __launch_bounds__(NT) LWK_STEP_OCC void lw_step_kernel(const InstDev 
     }
 }
 
+// Segment taken by block b of an n-block launch of one instance: the GPU deals
+// block b to XCD b mod 8; the blocks one XCD receives take consecutive
+// segments (XCD x owns the contiguous range after those of XCDs 0..x-1).
+MPA int xcd_segment(int b, int n) {
+    const int x = b % 8, r = b / 8, q = n / 8, rem = n % 8;
+    return x * q + min(x, rem) + r;
+}
+
 // ------------------------------------------------------------------ wide sweep
 // The G = NT / n_theta groups of a block take the columns of one r* segment
 // in turn, each lane a run of P consecutive columns of its theta row: in
@@ -827,7 +835,9 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
     constexpr int CH = W == 1 ? 1 : W;
     constexpr int RM = kMaxReach;
     extern __shared__ d2 xs[];
-    const WorkItem wi = items[blockIdx.x];
+    // items == nullptr: one instance, whose segments the blocks take in the
+    // XCD-aware order the host uses for work lists (see the host's xcd_order)
+    const WorkItem wi = items ? items[blockIdx.x] : WorkItem{0, xcd_segment(blockIdx.x, gridDim.x)};
     const InstDev &I = insts[wi.inst];
     const int nr = I.nr, nth = I.nth, R = I.reach, B = I.segcols;
     const int G = wide_groups(NT, nth), D = G + 1, RS = nth + 2 * RM;

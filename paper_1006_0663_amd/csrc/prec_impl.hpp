@@ -178,14 +178,17 @@ hipError_t wide_launch_k(size_t lds, const InstDev *insts, const WorkItem *items
     return hipGetLastError();
 }
 
-// unrolled variants (tm = 2, 3, 4) exist for blocks of 128..512 threads and,
-// in FP64, the per-point coefficient modes; everything else takes the loop
+// unrolled variants (tm = 1..4) exist for FP64 blocks of 128..512 threads in
+// the per-point coefficient modes; everything else takes the loop.
 template <class T, int NT, int P, int CM>
 hipError_t wide_launch_nt(int tm, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                           hipStream_t stream, bool attr_only) {
-    constexpr bool unrolled = NT >= 128 && NT <= 512 && (words_of<T>::value > 1 || CM > 0);
+    // (multiword types: the unrolled forms gain nothing for dd and lose ~25 %
+    // for qd, whose registers they exhaust; those take the loop)
+    constexpr bool unrolled = NT >= 128 && NT <= 512 && words_of<T>::value == 1 && CM > 0;
     if constexpr (unrolled) {
         switch (tm) {
+            case 1: return wide_launch_k<T, NT, P, CM, 1>(lds, insts, items, nitems, parity, stream, attr_only);
             case 2: return wide_launch_k<T, NT, P, CM, 2>(lds, insts, items, nitems, parity, stream, attr_only);
             case 3: return wide_launch_k<T, NT, P, CM, 3>(lds, insts, items, nitems, parity, stream, attr_only);
             case 4: return wide_launch_k<T, NT, P, CM, 4>(lds, insts, items, nitems, parity, stream, attr_only);
@@ -216,9 +219,9 @@ hipError_t wide_launch_o(int nt, int tm, size_t lds, const InstDev *insts, const
     return hipErrorInvalidValue;
 }
 
-// run = columns per lane and iteration (1, or 2 for FP64); cmode = coefficient
-// mode of lw_wide_kernel (1 and 2 for FP64 only); tm = unrolled iteration
-// count (2, 3, 4) when every work item needs at most that many, else 0
+// run = columns per lane and iteration (1, or 2 for FP64); cmode =
+// coefficient mode of lw_wide_kernel (1 and 2 for FP64 only); tm = unrolled
+// iteration count (1..4) when every work item needs at most that many, else 0
 template <class T>
 hipError_t wide_launch(int nt, int run, int cmode, int tm, size_t lds, const InstDev *insts, const WorkItem *items,
                        int nitems, int parity, hipStream_t stream, bool attr_only) {

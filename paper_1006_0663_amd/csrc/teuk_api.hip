@@ -147,14 +147,17 @@ hipError_t step_launch(const Batch &b, int parity) {
     }
     if (b.sweep != TEUK_SWEEP_SEGMENT) {
         const int run = wide_run(b.sweep);
+        // one instance: the kernel derives its segment from the block index
+        // (same order as the work list) and skips one dependent load
+        const lwk::WorkItem *items = b.inst.size() == 1 ? nullptr : b.d_items;
         switch (b.words) {
             case 1:
-                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream,
+                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, b.d_inst, items, b.nitems, parity, b.stream,
                                      false);
             case 2:
-                return lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+                return lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, b.d_inst, items, b.nitems, parity, b.stream, false);
             default:
-                return lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream, false);
+                return lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, b.d_inst, items, b.nitems, parity, b.stream, false);
         }
     }
     switch (b.words) {
@@ -195,7 +198,7 @@ int device_lds_limit() {
 // of the list, i.e. blocks first.. of the launch).  The GPU hands block b to
 // XCD b mod kXcds; the blocks one XCD receives get consecutive segments, so a
 // column two neighbouring segments both read is fetched through one L2.
-constexpr int kXcds = 8;
+constexpr int kXcds = 8;   // the kernels' lwk::xcd_segment computes the same order for one instance
 void xcd_order(std::vector<lwk::WorkItem> &items, size_t first, size_t n) {
     const std::vector<lwk::WorkItem> src(items.begin() + first, items.begin() + first + n);
     size_t cnt[kXcds] = {}, base[kXcds] = {}, seen[kXcds] = {};
@@ -253,7 +256,7 @@ int build_worklist(Batch &b) {
             const int K = std::min(b.segcols, I.g.n_r) + 2, per = (b.nt / I.g.n_theta) * wide_run(b.sweep);
             ti = std::max(ti, (K + per - 1) / per);
         }
-        b.tm = ti <= 2 ? 2 : (ti <= 4 ? ti : 0);
+        b.tm = ti <= 4 ? ti : 0;
         if (b.lds > 64 * 1024) {
             const int run = wide_run(b.sweep);
             hipError_t e =

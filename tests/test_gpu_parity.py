@@ -122,7 +122,8 @@ def test_batched_equals_single_bitwise():
 # groups per block, one group per block, segments of one node, ragged tails
 SHAPES = [(T.SWEEP_SEGMENT, 8, 0), (T.SWEEP_SEGMENT, 3, 64), (T.SWEEP_WIDE, 8, 0), (T.SWEEP_WIDE, 1, 0),
           (T.SWEEP_WIDE, 5, 64), (T.SWEEP_WIDE, 13, 256), (T.SWEEP_WIDE, 40, 0), (T.SWEEP_WIDE2, 8, 0),
-          (T.SWEEP_WIDE2, 1, 0), (T.SWEEP_WIDE2, 5, 64), (T.SWEEP_WIDE2, 11, 128), (T.SWEEP_WIDE2, 40, 512)]
+          (T.SWEEP_WIDE2, 1, 0), (T.SWEEP_WIDE2, 5, 64), (T.SWEEP_WIDE2, 11, 128), (T.SWEEP_WIDE2, 40, 512),
+          (T.SWEEP_WIDE, 13, 128), (T.SWEEP_WIDE2, 3, 256)]
 
 
 @pytest.mark.parametrize("words", [1, 2, 4])
