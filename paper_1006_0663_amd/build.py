@@ -10,8 +10,9 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libteuk.so")
 SOURCES = ["teuk_api.hip", "prec_f64.hip", "prec_dd.hip", "prec_qd.hip", "arith_hooks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# kernarg preload: the first kernel arguments arrive in SGPRs at wave launch
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-kernarg-preload-count=16",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

@@ -827,19 +827,35 @@ __device__ __forceinline__ cx<T> stencil_ghosted(const d2 *slot, int rs, int j, 
 // rows staged in LDS, 2 (FP64, n_theta a multiple of the wavefront size, so
 // a wavefront lies in one group and its column is uniform) per point from
 // radial rows read with scalar loads.
+// Launch arguments of a one-instance launch, passed by value so that the
+// state loads need no descriptor load first (they arrive with the kernel
+// arguments, preloaded into SGPRs where the hardware supports it).
+struct WideArgs {
+    const double *uin;
+    double *uout;
+    int nr, nth, segcols, blocks;
+};
+
 // TM > 0: at most TM iterations (the host checks), all loads issued up front.
-template <class T, int NT, int P, int CM, int TM>
-__global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__ insts,
+// ONE: a one-instance launch (items unused, geometry and state pointers from
+// wa; the blocks take the segments in the XCD-aware order of the host's
+// xcd_order); otherwise every block reads its work item and descriptor.
+template <class T, int NT, int P, int CM, int TM, bool ONE>
+__global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, double *wa_uout, int wa_nr, int wa_nth,
+                                                     int wa_segcols, int wa_blocks,
+                                                     const InstDev *__restrict__ insts,
                                                      const WorkItem *__restrict__ items, int parity) {
     constexpr int W = words_of<T>::value;
     constexpr int CH = W == 1 ? 1 : W;
     constexpr int RM = kMaxReach;
     extern __shared__ d2 xs[];
-    // items == nullptr: one instance, whose segments the blocks take in the
-    // XCD-aware order the host uses for work lists (see the host's xcd_order)
-    const WorkItem wi = items ? items[blockIdx.x] : WorkItem{0, xcd_segment(blockIdx.x, gridDim.x)};
+    // (the one-instance arguments are plain scalars, first in the list, so
+    // the hardware can preload them into SGPRs)
+    const WideArgs wa{wa_uin, wa_uout, wa_nr, wa_nth, wa_segcols, wa_blocks};
+    const WorkItem wi = ONE ? WorkItem{0, xcd_segment(blockIdx.x, wa.blocks)} : items[blockIdx.x];
     const InstDev &I = insts[wi.inst];
-    const int nr = I.nr, nth = I.nth, R = I.reach, B = I.segcols;
+    const int nr = ONE ? wa.nr : I.nr, nth = ONE ? wa.nth : I.nth, B = ONE ? wa.segcols : I.segcols;
+    const int R = I.reach;
     const int G = wide_groups(NT, nth), D = G + 1, RS = nth + 2 * RM;
     const int g = threadIdx.x / nth, j = threadIdx.x - g * nth;
     const bool lane_on = g < G;
@@ -855,12 +871,25 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
     d2 *const XLH = XL + D * CH * nth;              // L(half-step Phi), last column
     double *const lrow_f = (double *)(XLH + D * CH * nth);    // FP64 per-point: radial rows, nodes a..e
     double *const lrow_h = lrow_f + K * kRadRow;              //                 half nodes a..e-1
-    const GLB double *uin = gptr((const double *)I.u[parity]);
-    GLB double *uout = gptr(I.u[parity ^ 1]);
+    const GLB double *uin = gptr(ONE ? wa.uin : (const double *)I.u[parity]);
+    GLB double *uout = gptr(ONE ? wa.uout : I.u[parity ^ 1]);
     const GLB double *wtab = gptr(I.wt);
     const uint32_t plane = (uint32_t)nr * nth, hplane = (uint32_t)(nr - 1) * nth;
-    const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
     const int jj = lane_on ? j : 0;
+    // the run's columns, requested before anything that needs the descriptor
+    const int TI = (K + G * P - 1) / (G * P);       // iterations with columns (TM >= TI when TM > 0)
+    Pt<T> ua[TM > 0 ? TM : 1][P];
+    if constexpr (TM > 0) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int k = g * P + t * G * P + p;
+                ua[t][p] = (lane_on && t < TI && k < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k) * nth + j))
+                                                       : Pt<T>{};
+            }
+    }
+    const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
 
     double cs_j = 0.0, s2_j = 0.0;
     if constexpr (W == 1 && CM == 1) {
@@ -900,7 +929,6 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
         if (c1 == nr) gst_pt(uout, plane, (uint32_t)((nr - 1) * nth + j), zero);
     }
 
-    const int TI = (K + G * P - 1) / (G * P);       // iterations with columns (TM >= TI when TM > 0)
     int k0 = g * P, sk = lane_on ? g : 0;           // first column of this lane's run and the run's slot
     Pt<T> u_l[P], uh_l[P];                          // stage-2 operands kept from the previous iteration:
     cx<T> lh_l[P];                                  // u^n left of each column, half steps, their L
@@ -986,16 +1014,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const InstDev *__restrict__
         return true;
     };
     if constexpr (TM > 0) {
-        // every column of the lane requested up front: one memory latency per
-        // launch instead of one per iteration
-        Pt<T> ua[TM][P];
-#pragma unroll
-        for (int t = 0; t < TM; ++t)
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int k = k0 + t * G * P + p;
-                ua[t][p] = (lane_on && t < TI && k < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k) * nth + j)) : zero;
-            }
+        // every column of the lane was requested up front (above): one memory
+        // latency per launch instead of one per iteration
 #pragma unroll
         for (int t = 0; t <= TM; ++t)
             if (!iteration(t, ua[t < TM ? t : TM - 1])) break;

@@ -147,17 +147,26 @@ hipError_t step_launch(const Batch &b, int parity) {
     }
     if (b.sweep != TEUK_SWEEP_SEGMENT) {
         const int run = wide_run(b.sweep);
-        // one instance: the kernel derives its segment from the block index
-        // (same order as the work list) and skips one dependent load
-        const lwk::WorkItem *items = b.inst.size() == 1 ? nullptr : b.d_items;
+        // one instance: the launch arguments carry its geometry and state
+        // pointers and the kernel derives its segment from the block index
+        // (same order as the work list), so no load precedes the state loads
+        lwk::WideArgs one{};
+        const lwk::WideArgs *onep = nullptr;
+        if (b.inst.size() == 1) {
+            const Instance &I = b.inst[0];
+            one = {I.u[parity], I.u[parity ^ 1], I.g.n_r, I.g.n_theta, b.segcols, 0};
+            onep = &one;
+        }
         switch (b.words) {
             case 1:
-                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, b.d_inst, items, b.nitems, parity, b.stream,
-                                     false);
+                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
+                                     b.stream, false);
             case 2:
-                return lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, b.d_inst, items, b.nitems, parity, b.stream, false);
+                return lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity, b.stream,
+                                    false);
             default:
-                return lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, b.d_inst, items, b.nitems, parity, b.stream, false);
+                return lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity, b.stream,
+                                    false);
         }
     }
     switch (b.words) {
@@ -259,10 +268,15 @@ int build_worklist(Batch &b) {
         b.tm = ti <= 4 ? ti : 0;
         if (b.lds > 64 * 1024) {
             const int run = wide_run(b.sweep);
-            hipError_t e =
-                b.words == 1 ? lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
-                : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, nullptr, nullptr, 0, 0, nullptr, true)
-                               : lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, nullptr, nullptr, 0, 0, nullptr, true);
+            // both the one-instance and the work-list form
+            const lwk::WideArgs one{};
+            hipError_t e = hipSuccess;
+            for (const lwk::WideArgs *o : {&one, (const lwk::WideArgs *)nullptr}) {
+                if (e != hipSuccess) break;
+                e = b.words == 1 ? lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
+                    : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
+                                   : lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true);
+            }
             if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(dynamic LDS)");
         }
     } else {
