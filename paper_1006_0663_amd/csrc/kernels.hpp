@@ -948,9 +948,9 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         const bool last_on = lane_on && k0 + P - 1 < K;
         if (last_on) xput<T>(XPI + sk * CH * nth, nth, j, u_c[P - 1].pi);
         __syncthreads();                                                        // B1
-        // Stages run on every lane with clamped indices (results of idle lanes
-        // and of columns outside the segment are discarded); only the stores
-        // are conditional, which keeps each phase one basic block.
+        // FP64 stages run on every lane with clamped indices (results of idle
+        // lanes and of columns outside the segment are discarded); only the
+        // stores are conditional, which keeps each phase one basic block.
         if (t >= 1) {
             // stage 2 (lw2) at node a + kp - 1 for the columns kp of the previous run
             const int k0p = k0 - G * P;
@@ -961,6 +961,10 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int kp = k0p + p, i = a + kp - 1;
+                const bool on = lane_on && kp >= 2 && kp < K;
+                // (FP64 computes on every lane; the multiword types skip whole
+                // wavefronts with nothing to do, which saves far more there)
+                if (W > 1 && !on) continue;
                 const int ic = min(max(i, a), e);
                 const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
                 const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
@@ -968,7 +972,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                 coef(false, ic, cf);
                 const Pt<T> un =
                     lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
-                if (lane_on && kp >= 2 && kp < K) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
+                if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
             }
         }
         if (t == TI) return false;
@@ -987,6 +991,9 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
             for (int p = 0; p < P; ++p) {
                 // stage 1 (lw1) at half node a + k - 1/2 (half index a + k - 1)
                 const int k = k0 + p, h = a + k - 1;
+                const bool on = lane_on && k >= 1 && k < K;
+                uh[p] = zero;
+                if (W > 1 && !on) continue;
                 const int hc = min(max(h, a), e - 1);
                 const Pt<T> &ua = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
                 const cx<T> &la = p == 0 ? l_m1 : l_c[p > 0 ? p - 1 : 0];
@@ -994,7 +1001,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                 coef(true, hc, cf);
                 const Pt<T> bar = pt_avg(ua, u_c[p]);
                 uh[p] = lw_stage(bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), cf, hdt);
-                if (lane_on && k >= 1 && k < K) xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
+                if (on) xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
             }
             if (last_on && k0 + P - 1 >= 1) xput<T>(XHI + sk * CH * nth, nth, j, uh[P - 1].pi);
         }
