@@ -65,7 +65,9 @@ enum {
 };
 
 // 1/sqrt(x), x > 0, to about one ulp: the hardware reciprocal square root
-// seeds two Newton steps on the device; the host starts from 1/sqrt(x).
+// seeds two Newton steps on the device; the host starts from 1/sqrt(x).  The
+// step y(3/2 - x y^2/2) is written y + y(1/2 - x y^2/2), whose constants are
+// inline operands of the FMA.
 MPA double rsqrt_nr(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
     double y = __builtin_amdgcn_rsq(x);
@@ -73,23 +75,25 @@ MPA double rsqrt_nr(double x) {
     double y = 1.0 / sqrt(x);
 #endif
     const double hx = 0.5 * x;
-    y = y * fma(-hx, y * y, 1.5);
-    y = y * fma(-hx, y * y, 1.5);
+    y = fma(y, fma(-hx, y * y, 0.5), y);
+    y = fma(y, fma(-hx, y * y, 0.5), y);
     return y;
 }
 
+// (Every operation takes at most one row value: where the rows sit in
+// scalar registers, an instruction can read only one of them.)
 template <class RowPtr>
 MPA void coef_fp64_point(RowPtr rr, double cs, double s2, double *c) {
-    const double X = fma(-rr[kA2D], s2, rr[kVp2]);
+    const double X = rr[kVp2] - rr[kA2D] * s2;
     const double rq = rsqrt_nr(X);
     const double q = rq * rq;
     const double b = rr[kVp] * rq;
     c[0] = rr[kSIVp] * rq;
     c[1] = rr[kSD] * q;
-    c[2] = q * fma(s2 * q, rr[kSIT8], -fma(b, rr[kSIT1], rr[kSIT6]));
-    c[3] = -q * fma(b, fma(rr[kSIT3], cs, rr[kSIT2]), rr[kSIT7]);
+    c[2] = q * fma(s2 * q, rr[kSIT8], -(b * rr[kSIT1] + rr[kSIT6]));
+    c[3] = -q * fma(b, cs * rr[kSIT3] + rr[kSIT2], rr[kSIT7]);
     c[4] = q * rr[kST1];
-    c[5] = q * fma(rr[kST3], cs, rr[kST2]);
+    c[5] = q * (cs * rr[kST3] + rr[kST2]);
     c[6] = q * rr[kST4];
     c[7] = q * rr[kST5];
 }

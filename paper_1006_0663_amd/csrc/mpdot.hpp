@@ -27,7 +27,9 @@ namespace lwk {
 template <class T> struct Acc;
 
 template <> struct Acc<double> {
-    double s = 0.0;
+    // starts at -0: -0 + v == v and fma(a, b, -0) == a*b for every v, a*b
+    // (signed zeros included), so the compiler drops the first addition
+    double s = -0.0;
     MPA void prod(double a, double b) { s = fma(a, b, s); }
     MPA void value(double v) { s += v; }
     MPA double result() const { return s; }
