@@ -29,8 +29,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # the launch shape and kernel sources they were taken with: `source` is
 # kernel_source_digest() at that time; otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "shape": (2, 4, 128), "source": "909148a8630a",
-    "fetch_kib": 9425.4, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0,
+    "shape": (2, 4, 128), "source": "f9e0cab04282",
+    "fetch_kib": 9426.8, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0,
 }
 
 
