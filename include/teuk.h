@@ -144,7 +144,8 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
  *   column is computed once;
  * TEUK_SWEEP_WIDE2: the same with each lane taking two neighbouring columns
  *   per turn (FP64 only; TEUK_ENOTSUP otherwise).
- * -1 restores the default (wide).  Resets the
+ * -1 restores the default: wide, or segment where the wide sweep's exchange
+ * slots would exceed 64 KiB of LDS (large n_theta in dd and qd).  Resets the
  * block size to the default.  teuk_get_sweep returns the sweep in use. */
 int teuk_set_sweep(teuk_t *h, int sweep);
 int teuk_get_sweep(const teuk_t *h);

@@ -257,8 +257,17 @@ int build_worklist(Batch &b) {
             while (nt / 2 >= maxnth && wide_lds(b, nt) > cap) nt /= 2;
             b.nt = nt;
             b.lds = wide_lds(b, nt);
-            if (b.lds > lim) return fail(TEUK_EINVAL, "n_theta too large for the device's LDS");
+            if (b.lds > 64 * 1024 && b.sweep_req < 0) {
+                // default sweep only: wide slots for this n_theta and precision
+                // would need more than 64 KiB of LDS; the segment sweep does not
+                b.sweep = TEUK_SWEEP_SEGMENT;
+                b.lds = 0;
+            } else if (b.lds > lim) {
+                return fail(TEUK_EINVAL, "n_theta too large for the device's LDS");
+            }
         }
+    }
+    if (b.sweep != TEUK_SWEEP_SEGMENT) {
         // iterations a work item needs: its columns over the columns a block takes per iteration
         int ti = 0;
         for (auto &I : b.inst) {

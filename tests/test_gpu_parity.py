@@ -162,6 +162,26 @@ def test_fp64_coefficient_row_modes_are_bitwise(sweep, monkeypatch):
     assert rel_linf(got, oracle_run(w, fields, 8)) <= TOL[1]
 
 
+@pytest.mark.parametrize("words", [1, 2, 4])
+def test_largest_theta_grid(words):
+    """n_theta = 256, the largest the library takes: the default sweep (wide where
+    its slots fit in 64 KiB of LDS, else segment) against the oracle, and every
+    sweep that accepts the grid gives the same bits."""
+    w = inputs.C1.with_(n_r=13, n_theta=256, rstar_min=90.0, rstar_max=110.0, words=words, m=2, a_over_M=0.6)
+    fields = inputs.initial_fields(w)
+    _note("n_theta 256 words=%d" % words)
+    got = _run_gpu(w, fields, 4, tile=5)
+    assert rel_linf(got, oracle_run(w, fields, 4)) <= TOL[words]
+    for sweep in ([T.SWEEP_SEGMENT, T.SWEEP_WIDE] + ([T.SWEEP_WIDE2] if words == 1 else [])):
+        try:
+            other = _run_gpu(w, fields, 4, tile=5, sweep=sweep)
+        except T.TeukError as ex:           # wide slots beyond the device's LDS
+            _note("  sweep %d not available: %s" % (sweep, ex))
+            continue
+        for f in range(4):
+            assert np.array_equal(got[f], other[f]), (sweep, f)
+
+
 def test_wide2_rejected_for_multiword():
     w = inputs.C1.with_(n_r=20, n_theta=8, words=2)
     h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 2)
