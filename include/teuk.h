@@ -150,6 +150,16 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
 int teuk_set_sweep(teuk_t *h, int sweep);
 int teuk_get_sweep(const teuk_t *h);
 
+/* Time steps per kernel launch (1, 2 or 4; results are bitwise the same).
+ * With k > 1 each launch advances k steps of a segment from registers,
+ * reading k extra columns on each side (so small grids, whose steps are bound
+ * by launch and memory latency, take fewer of both).  Needs the wide sweep
+ * with runs of one column, dd or FP64 with per-point coefficients, blocks of
+ * 128..512 threads and segcols + 3k <= 2 * block / n_theta; otherwise
+ * TEUK_EINVAL and the previous setting stays.  teuk_step(n) runs n / k fused
+ * launches and the remainder one step per launch. */
+int teuk_set_fuse(teuk_t *h, int steps_per_launch);
+
 /* Test hooks: the eight scaled coefficients at half nodes (which = 0,
  * [8][n_theta][n_r-1][p]) or nodes (which = 1, [8][n_theta][n_r][p]), or the
  * angular weights (which = 2, [2R+1][n_theta][p]).  Order of the eight:
@@ -175,7 +185,10 @@ double teuk_batch_dt(const teuk_batch_t *b, int k);
 int teuk_batch_set_tile(teuk_batch_t *b, int segcols);
 int teuk_batch_set_launch(teuk_batch_t *b, int segcols, int block);
 int teuk_batch_set_sweep(teuk_batch_t *b, int sweep);
-/* Capture the step loop in a HIP graph of `steps_per_graph` launches (0 = off). */
+int teuk_batch_set_fuse(teuk_batch_t *b, int steps_per_launch);
+/* Capture the step loop in HIP graphs of about `steps_per_graph` steps (0 = off):
+ * an even number of launches, so every replay starts from the state buffer it
+ * was captured on; steps that do not fill a graph are launched directly. */
 int teuk_batch_use_graph(teuk_batch_t *b, int steps_per_graph);
 int teuk_use_graph(teuk_t *h, int steps_per_graph);
 

@@ -45,16 +45,21 @@ hipError_t step_qd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts
 // come from: 0 stored planes, 1 radial rows staged in LDS, 2 radial rows by
 // scalar loads (n_theta a multiple of 64); tm = 2, 3 or 4 selects the variant
 // with that many iterations unrolled and all loads issued up front (every
-// work item must need at most tm iterations), 0 the loop; one = arguments of a
+// work item must need at most tm iterations), 0 the loop; ns = time steps per
+// launch (1; 2 or 4 for FP64 with per-point coefficients and dd, runs of one
+// column, tm <= 2); one = arguments of a
 // one-instance launch (or nullptr: the work list); one work item is one segment of the
 // descriptor's segcols nodes; lds = dynamic LDS bytes (exchange arrays plus
 // the FP64 radial rows).  attr_only: only enable `lds` bytes of dynamic LDS
 // for that kernel (needed above 64 KiB), launch nothing.
-hipError_t wide_f64(int nt, int run, int cmode, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
-                    const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only);
-hipError_t wide_dd(int nt, int run, int cmode, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
-                    const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only);
-hipError_t wide_qd(int nt, int run, int cmode, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
-                    const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only);
+hipError_t wide_f64(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
+                    const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
+                    bool attr_only);
+hipError_t wide_dd(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
+                    const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
+                    bool attr_only);
+hipError_t wide_qd(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
+                    const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
+                    bool attr_only);
 
 }  // namespace lwk

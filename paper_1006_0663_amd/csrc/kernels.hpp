@@ -844,7 +844,13 @@ struct WideArgs {
 // ONE: a one-instance launch (items unused, geometry and state pointers from
 // wa; the blocks take the segments in the XCD-aware order of the host's
 // xcd_order); otherwise every block reads its work item and descriptor.
-template <class T, int NT, int P, int CM, int TM, bool ONE>
+// NS > 1 (with TM > 0): NS steps per launch.  The block reads NS columns on
+// each side of its segment; after every step the stage-2 results stay in the
+// lanes' registers (shifted one node left: a lane's stage 2 is at the node left
+// of its column) and the valid range shrinks by one column at each side that
+// is not a domain boundary.  At the right domain boundary NS extra columns
+// carry node n_r - 1 as it shifts; boundary nodes are reset to zero each step.
+template <class T, int NT, int P, int CM, int TM, bool ONE, int NS>
 __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, double *wa_uout, int wa_nr, int wa_nth,
                                                      int wa_segcols, int wa_blocks,
                                                      const InstDev *__restrict__ insts,
@@ -852,6 +858,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     constexpr int W = words_of<T>::value;
     constexpr int CH = W == 1 ? 1 : W;
     constexpr int RM = kMaxReach;
+    static_assert(NS == 1 || TM > 0, "fused steps need the unrolled form");
     extern __shared__ d2 xs[];
     // (the one-instance arguments are plain scalars, first in the list, so
     // the hardware can preload them into SGPRs)
@@ -864,8 +871,9 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     const int g = threadIdx.x / nth, j = threadIdx.x - g * nth;
     const bool lane_on = g < G;
     const int c0 = wi.group * B, c1 = min(c0 + B, nr);
-    const int a = max(c0, 1) - 1, e = min(c1, nr - 1);
-    const int K = e - a + 1;                        // columns a..e
+    const int a = max(c0 - NS, 0), e = min(c1 - 1 + NS, nr - 1);
+    const int KR = e - a + 1;                       // columns a..e (nodes that exist)
+    const int K = KR + ((NS > 1 && e == nr - 1) ? NS : 0);
     const int SP = P * CH * RS;                     // doubles-pairs per ghosted slot
     d2 *const XP = xs;                              // Phi^n        [slot][p][chunk][RS]
     d2 *const XH = XP + D * SP;                     // half-step Phi
@@ -874,7 +882,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     d2 *const XL = XHI + D * CH * nth;              // L(Phi^n), last column
     d2 *const XLH = XL + D * CH * nth;              // L(half-step Phi), last column
     double *const lrow_f = (double *)(XLH + D * CH * nth);    // FP64 per-point: radial rows, nodes a..e
-    double *const lrow_h = lrow_f + K * kRadRow;              //                 half nodes a..e-1
+    double *const lrow_h = lrow_f + KR * kRadRow;             //                 half nodes a..e-1
     const GLB double *uin = gptr(ONE ? wa.uin : (const double *)I.u[parity]);
     GLB double *uout = gptr(ONE ? wa.uout : I.u[parity ^ 1]);
     const GLB double *wtab = gptr(I.wt);
@@ -889,15 +897,15 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int k = g * P + t * G * P + p;
-                ua[t][p] = (lane_on && t < TI && k < K) ? gld_pt<T>(uin, plane, (uint32_t)((a + k) * nth + j))
-                                                       : Pt<T>{};
+                ua[t][p] = (lane_on && t < TI && k < KR) ? gld_pt<T>(uin, plane, (uint32_t)((a + k) * nth + j))
+                                                        : Pt<T>{};
             }
     }
     const T hdt = from_words<T>(I.hdt), dt = from_words<T>(I.dt);
 
     double cs_j = 0.0, s2_j = 0.0;
     if constexpr (W == 1 && CM == 1) {
-        const int nf = K * kRadRow, nh = (K - 1) * kRadRow;
+        const int nf = KR * kRadRow, nh = (KR - 1) * kRadRow;
         const GLB double *rf = gptr(I.rf) + a * kRadRow, *rh = gptr(I.rh) + a * kRadRow;
         for (int q = threadIdx.x; q < nf + nh; q += NT) lrow_f[q] = q < nf ? rf[q] : rh[q - nf];
     }
@@ -943,7 +951,10 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         lh_l[p] = zero.phi;
     }
     // iteration t on the run's columns u_c; false once the last stage 2 is done
-    auto iteration = [&](int t, const Pt<T> *u_c) -> bool {
+    int as = a;                                     // node of column 0 in the current step
+    // iteration t on the run's columns u_c; stage 2 of the previous run goes to
+    // global memory in the last step, else (fused steps) to u_out
+    auto iteration = [&](int t, const Pt<T> *u_c, Pt<T> *u_out, bool last) -> bool {
         const int sl = sk == 0 ? G : sk - 1;        // slot of the run to the left
         d2 *const xp = XP + sk * SP, *const xh = XH + sk * SP;
 #pragma unroll
@@ -964,19 +975,25 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
             const cx<T> lh_m = xget<T>(XLH + sk * CH * nth, nth, jj);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                const int kp = k0p + p, i = a + kp - 1;
+                const int kp = k0p + p, i = as + kp - 1;
                 const bool on = lane_on && kp >= 2 && kp < K;
                 // (FP64 computes on every lane; the multiword types skip whole
                 // wavefronts with nothing to do, which saves far more there)
-                if (W > 1 && !on) continue;
-                const int ic = min(max(i, a), e);
-                const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
-                const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
-                T cf[8];
-                coef(false, ic, cf);
-                const Pt<T> un =
-                    lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
-                if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
+                Pt<T> un = zero;
+                if (W == 1 || on) {
+                    const int ic = min(max(i, a), e);
+                    const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
+                    const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
+                    T cf[8];
+                    coef(false, ic, cf);
+                    un = lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
+                }
+                if (last) {
+                    // nodes of the segment, radial boundary excluded
+                    if (lane_on && i >= max(c0, 1) && i < min(c1, nr - 1)) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
+                } else if constexpr (NS > 1) {
+                    u_out[p] = (i == 0 || i == nr - 1) ? zero : un;
+                }
             }
         }
         if (t == TI) return false;
@@ -994,7 +1011,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 // stage 1 (lw1) at half node a + k - 1/2 (half index a + k - 1)
-                const int k = k0 + p, h = a + k - 1;
+                const int k = k0 + p, h = as + k - 1;
                 const bool on = lane_on && k >= 1 && k < K;
                 uh[p] = zero;
                 if (W > 1 && !on) continue;
@@ -1028,8 +1045,14 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         // every column of the lane was requested up front (above): one memory
         // latency per launch instead of one per iteration
 #pragma unroll
-        for (int t = 0; t <= TM; ++t)
-            if (!iteration(t, ua[t < TM ? t : TM - 1])) break;
+        for (int st = 0; st < NS; ++st) {
+#pragma unroll
+            for (int t = 0; t <= TM; ++t)
+                if (!iteration(t, ua[t < TM ? t : TM - 1], ua[t > 0 ? t - 1 : 0], st == NS - 1)) break;
+            k0 = g * P;                             // next step: same lanes, same slots,
+            sk = lane_on ? g : 0;                   // columns one node further left
+            --as;
+        }
     } else {
         Pt<T> u_next[P];
 #pragma unroll
@@ -1043,7 +1066,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                 const int kn = k0 + G * P + p;
                 if (lane_on && kn < K) u_next[p] = gld_pt<T>(uin, plane, (uint32_t)((a + kn) * nth + j));
             }
-            if (!iteration(t, u_c)) break;
+            if (!iteration(t, u_c, nullptr, true)) break;
         }
     }
 }

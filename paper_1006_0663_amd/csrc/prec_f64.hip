@@ -7,9 +7,10 @@ hipError_t step_f64(int nt, int seg, bool onfly, size_t lds, const InstDev *inst
                    hipStream_t stream) {
     return step_launch<double>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);
 }
-hipError_t wide_f64(int nt, int run, int cmode, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
-                    const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only) {
-    return wide_launch<double>(nt, run, cmode, tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+hipError_t wide_f64(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
+                    const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
+                    bool attr_only) {
+    return wide_launch<double>(nt, run, cmode, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
 }
 hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, const double *trig, double *cf,
                        double *ch, hipStream_t stream) {

@@ -167,63 +167,91 @@ hipError_t step_launch(int nt, int seg, bool onfly, size_t lds, const InstDev *i
 
 // ---- wide sweep (see lw_wide_kernel)
 // one != nullptr: a one-instance launch whose arguments carry the geometry
-// and state pointers (FP64; the multiword types read them from the descriptor)
-template <class T, int NT, int P, int CM, int TM>
-hipError_t wide_launch_k(size_t lds, const WideArgs *one, const InstDev *insts, const WorkItem *items, int nitems,
-                         int parity, hipStream_t stream, bool attr_only) {
-    constexpr bool has_one = words_of<T>::value == 1;
-    if (attr_only) {
-        // dynamic LDS beyond the default 64 KiB has to be enabled per kernel
-        if (has_one && one)
-            return hipFuncSetAttribute((const void *)lw_wide_kernel<T, NT, P, CM, TM, has_one>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        return hipFuncSetAttribute((const void *)lw_wide_kernel<T, NT, P, CM, TM, false>,
+// and state pointers (FP64; the multiword types read them from the descriptor).
+// ns = steps per launch (1, or 2 and 4 for the fused forms that exist:
+// runs of one column, tm <= 2, FP64 per-point coefficients or dd).
+template <class T, int NT, int P, int CM, int TM, bool ONE1, int NS>
+hipError_t wide_launch_one(size_t lds, const WideArgs *one, const InstDev *insts, const WorkItem *items, int nitems,
+                           int parity, hipStream_t stream, bool attr_only) {
+    if (attr_only)
+        return hipFuncSetAttribute((const void *)lw_wide_kernel<T, NT, P, CM, TM, ONE1, NS>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    }
-    if (has_one && one)
-        lw_wide_kernel<T, NT, P, CM, TM, has_one><<<nitems, NT, lds, stream>>>(
+    if (ONE1)
+        lw_wide_kernel<T, NT, P, CM, TM, ONE1, NS><<<nitems, NT, lds, stream>>>(
             one->uin, one->uout, one->nr, one->nth, one->segcols, nitems, insts, items, parity);
     else
-        lw_wide_kernel<T, NT, P, CM, TM, false><<<nitems, NT, lds, stream>>>(nullptr, nullptr, 0, 0, 0, 0, insts,
-                                                                               items, parity);
+        lw_wide_kernel<T, NT, P, CM, TM, ONE1, NS><<<nitems, NT, lds, stream>>>(nullptr, nullptr, 0, 0, 0, 0, insts,
+                                                                                  items, parity);
     return hipGetLastError();
+}
+
+template <class T, int NT, int P, int CM, int TM>
+hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev *insts, const WorkItem *items,
+                         int nitems, int parity, hipStream_t stream, bool attr_only) {
+    constexpr int W = words_of<T>::value;
+    constexpr bool has_one = W == 1;
+    constexpr bool fused = TM >= 1 && TM <= 2 && P == 1 && (W == 2 || (W == 1 && CM > 0));
+    const bool o = has_one && one;
+    if (ns == 1) {
+        if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 1>(lds, one, insts, items, nitems, parity, stream, attr_only);
+        return wide_launch_one<T, NT, P, CM, TM, false, 1>(lds, one, insts, items, nitems, parity, stream, attr_only);
+    }
+    if constexpr (fused) {
+        if (ns == 2) {
+            if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
+            return wide_launch_one<T, NT, P, CM, TM, false, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
+        }
+        if (ns == 4) {
+            if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
+            return wide_launch_one<T, NT, P, CM, TM, false, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 // unrolled variants (tm = 1..4) exist for FP64 blocks of 128..512 threads in
 // the per-point coefficient modes; everything else takes the loop.
 template <class T, int NT, int P, int CM>
-hipError_t wide_launch_nt(int tm, size_t lds, const WideArgs *one, const InstDev *insts, const WorkItem *items,
+hipError_t wide_launch_nt(int tm, int ns, size_t lds, const WideArgs *one, const InstDev *insts, const WorkItem *items,
                           int nitems, int parity, hipStream_t stream, bool attr_only) {
-    // (multiword types: the unrolled forms gain nothing for dd and lose ~25 %
-    // for qd, whose registers they exhaust; those take the loop)
-    constexpr bool unrolled = NT >= 128 && NT <= 512 && words_of<T>::value == 1 && CM > 0;
+    // (multiword types: the unrolled forms lose ~25 % for qd, whose registers
+    // they exhaust, and gain nothing for dd beyond two iterations; qd always
+    // takes the loop, dd unrolls one or two iterations, which fused steps need)
+    constexpr int W = words_of<T>::value;
+    constexpr bool unrolled = NT >= 128 && NT <= 512 && ((W == 1 && CM > 0) || W == 2);
     if constexpr (unrolled) {
         switch (tm) {
-            case 1: return wide_launch_k<T, NT, P, CM, 1>(lds, one, insts, items, nitems, parity, stream, attr_only);
-            case 2: return wide_launch_k<T, NT, P, CM, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
-            case 3: return wide_launch_k<T, NT, P, CM, 3>(lds, one, insts, items, nitems, parity, stream, attr_only);
-            case 4: return wide_launch_k<T, NT, P, CM, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
+            case 1: return wide_launch_k<T, NT, P, CM, 1>(ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+            case 2: return wide_launch_k<T, NT, P, CM, 2>(ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+            case 3:
+                if constexpr (W == 1)
+                    return wide_launch_k<T, NT, P, CM, 3>(ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+                break;
+            case 4:
+                if constexpr (W == 1)
+                    return wide_launch_k<T, NT, P, CM, 4>(ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+                break;
             default: break;
         }
     }
-    return wide_launch_k<T, NT, P, CM, 0>(lds, one, insts, items, nitems, parity, stream, attr_only);
+    return wide_launch_k<T, NT, P, CM, 0>(ns, lds, one, insts, items, nitems, parity, stream, attr_only);
 }
 
 template <class T, int P, int CM>
-hipError_t wide_launch_o(int nt, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
+hipError_t wide_launch_o(int nt, int tm, int ns, size_t lds, const WideArgs *one, const InstDev *insts,
                          const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only) {
     constexpr int W = words_of<T>::value;
     switch (nt) {
-        case 64: return wide_launch_nt<T, 64, P, CM>(tm, lds, one, insts, items, nitems, parity, stream, attr_only);
-        case 128: return wide_launch_nt<T, 128, P, CM>(tm, lds, one, insts, items, nitems, parity, stream, attr_only);
-        case 256: return wide_launch_nt<T, 256, P, CM>(tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+        case 64: return wide_launch_nt<T, 64, P, CM>(tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+        case 128: return wide_launch_nt<T, 128, P, CM>(tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+        case 256: return wide_launch_nt<T, 256, P, CM>(tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
         case 512:
             if constexpr (W <= 2)
-                return wide_launch_nt<T, 512, P, CM>(tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+                return wide_launch_nt<T, 512, P, CM>(tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
             break;
         case 1024:
             if constexpr (W == 1 && P == 1)
-                return wide_launch_nt<T, 1024, P, CM>(tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+                return wide_launch_nt<T, 1024, P, CM>(tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
             break;
         default: break;
     }
@@ -232,15 +260,17 @@ hipError_t wide_launch_o(int nt, int tm, size_t lds, const WideArgs *one, const 
 
 // run = columns per lane and iteration (1, or 2 for FP64); cmode =
 // coefficient mode of lw_wide_kernel (1 and 2 for FP64 only); tm = unrolled
-// iteration count (1..4) when every work item needs at most that many, else 0
+// iteration count (1..4) when every work item needs at most that many, else 0;
+// ns = steps per launch (see wide_launch_k)
 template <class T>
-hipError_t wide_launch(int nt, int run, int cmode, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
-                       const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only) {
+hipError_t wide_launch(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
+                       const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
+                       bool attr_only) {
     if (!attr_only && nitems <= 0) return hipSuccess;
     if constexpr (words_of<T>::value == 1) {
 #define LWK_WIDE(P_, CM_)                                                                                     \
     if (run == P_ && cmode == CM_)                                                                             \
-        return wide_launch_o<T, P_, CM_>(nt, tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+        return wide_launch_o<T, P_, CM_>(nt, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
         LWK_WIDE(1, 0)
         LWK_WIDE(1, 1)
         LWK_WIDE(1, 2)
@@ -251,7 +281,7 @@ hipError_t wide_launch(int nt, int run, int cmode, int tm, size_t lds, const Wid
         return hipErrorInvalidValue;
     } else {
         if (run != 1 || cmode != 0) return hipErrorInvalidValue;
-        return wide_launch_o<T, 1, 0>(nt, tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+        return wide_launch_o<T, 1, 0>(nt, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
     }
 }
 

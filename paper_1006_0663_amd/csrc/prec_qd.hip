@@ -7,8 +7,9 @@ hipError_t step_qd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts
                    hipStream_t stream) {
     return step_launch<qd>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);
 }
-hipError_t wide_qd(int nt, int run, int cmode, int tm, size_t lds, const WideArgs *one, const InstDev *insts,
-                    const WorkItem *items, int nitems, int parity, hipStream_t stream, bool attr_only) {
-    return wide_launch<qd>(nt, run, cmode, tm, lds, one, insts, items, nitems, parity, stream, attr_only);
+hipError_t wide_qd(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
+                    const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
+                    bool attr_only) {
+    return wide_launch<qd>(nt, run, cmode, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
 }
 }  // namespace lwk

@@ -83,6 +83,7 @@ struct Batch {
     int sweep = 0;           // sweep in use
     int cmode = 0;           // wide sweep: coefficient mode (see lwk::wide_launch)
     int tm = 0;              // wide sweep: unrolled iteration count (0 = loop)
+    int fuse = 1;            // time steps per launch (wide sweep)
     bool no_scalar_rows = std::getenv("TEUK_NO_SCALAR_ROWS") != nullptr;   // diagnostics: force LDS rows
     size_t lds = 0;          // dynamic LDS bytes per block of the step kernel
     lwk::InstDev *d_inst = nullptr;
@@ -138,7 +139,7 @@ hipError_t coef_pass(int words, lwk::CoefJob &job, hipStream_t st) {
 // columns per lane and iteration of a wide sweep
 int wide_run(int sweep) { return sweep == TEUK_SWEEP_WIDE2 ? 2 : 1; }
 
-hipError_t step_launch(const Batch &b, int parity) {
+hipError_t step_launch(const Batch &b, int parity, int ns) {
     bool onfly = true;
     for (auto &I : b.inst) onfly = onfly && I.onfly;
     if (b.words == 1 && !onfly) {
@@ -159,16 +160,17 @@ hipError_t step_launch(const Batch &b, int parity) {
         }
         switch (b.words) {
             case 1:
-                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
+                return lwk::wide_f64(b.nt, run, b.cmode, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
                                      b.stream, false);
             case 2:
-                return lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity, b.stream,
-                                    false);
+                return lwk::wide_dd(b.nt, run, 0, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
+                                    b.stream, false);
             default:
-                return lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity, b.stream,
-                                    false);
+                return lwk::wide_qd(b.nt, run, 0, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
+                                    b.stream, false);
         }
     }
+    if (ns != 1) return hipErrorInvalidValue;         // the segment sweep takes one step per launch
     switch (b.words) {
         case 1: return lwk::step_f64(b.nt, b.segcols, onfly, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
         case 2: return lwk::step_dd(b.nt, b.segcols, false, b.lds, b.d_inst, b.d_items, b.nitems, parity, b.stream);
@@ -189,7 +191,7 @@ size_t wide_lds(const Batch &b, int nt) {
             case 2: x = lwk::wide_xchg_bytes<lwk::dd>(nt, I.g.n_theta, run); break;
             default: x = lwk::wide_xchg_bytes<lwk::qd>(nt, I.g.n_theta, run); break;
         }
-        if (b.cmode == 1) x += lwk::wide_rows_bytes(b.segcols);
+        if (b.cmode == 1) x += lwk::wide_rows_bytes(b.segcols + 2 * b.fuse);
         need = std::max(need, x);
     }
     return need;
@@ -241,7 +243,7 @@ int build_worklist(Batch &b) {
         }
         b.cmode = !onfly ? 0 : (wave_cols && !b.no_scalar_rows ? 2 : 1);
         // FP64 radial rows of a segment stay within kMaxRowsLds
-        while (b.segcols > 1 && lwk::wide_rows_bytes(b.segcols) > kMaxRowsLds) b.segcols -= 1;
+        while (b.segcols > 1 && lwk::wide_rows_bytes(b.segcols + 2 * b.fuse) > kMaxRowsLds) b.segcols -= 1;
         const size_t lim = (size_t)device_lds_limit();
         if (b.nt_req) {
             if (b.nt_req > max_wide_block(b.words)) return fail(TEUK_EINVAL, "block too large for this precision");
@@ -269,12 +271,23 @@ int build_worklist(Batch &b) {
     }
     if (b.sweep != TEUK_SWEEP_SEGMENT) {
         // iterations a work item needs: its columns over the columns a block takes per iteration
+        // (fused steps read fuse columns on each side, plus fuse columns
+        // past the right domain boundary)
         int ti = 0;
         for (auto &I : b.inst) {
-            const int K = std::min(b.segcols, I.g.n_r) + 2, per = (b.nt / I.g.n_theta) * wide_run(b.sweep);
+            const int K = std::min(b.segcols, I.g.n_r) + 2 * b.fuse + (b.fuse > 1 ? b.fuse : 0);
+            const int per = (b.nt / I.g.n_theta) * wide_run(b.sweep);
             ti = std::max(ti, (K + per - 1) / per);
         }
         b.tm = ti <= 4 ? ti : 0;
+        if (b.fuse > 1) {
+            const bool ok = b.tm >= 1 && b.tm <= 2 && wide_run(b.sweep) == 1 && b.nt >= 128 && b.nt <= 512 &&
+                            (b.words == 2 || (b.words == 1 && b.cmode > 0));
+            if (!ok)
+                return fail(TEUK_EINVAL, "fused steps need dd or FP64 per-point coefficients, runs of one column, "
+                                         "blocks of 128-512 threads and at most two iterations per step "
+                                         "(segcols + 3 * fuse <= 2 * block / n_theta)");
+        }
         if (b.lds > 64 * 1024) {
             const int run = wide_run(b.sweep);
             // both the one-instance and the work-list form
@@ -282,13 +295,18 @@ int build_worklist(Batch &b) {
             hipError_t e = hipSuccess;
             for (const lwk::WideArgs *o : {&one, (const lwk::WideArgs *)nullptr}) {
                 if (e != hipSuccess) break;
-                e = b.words == 1 ? lwk::wide_f64(b.nt, run, b.cmode, b.tm, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
-                    : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.tm, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
-                                   : lwk::wide_qd(b.nt, run, 0, b.tm, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true);
+                for (int ns : {1, b.fuse}) {
+                    if (e != hipSuccess) break;
+                    e = b.words == 1
+                            ? lwk::wide_f64(b.nt, run, b.cmode, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
+                        : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
+                                       : lwk::wide_qd(b.nt, run, 0, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true);
+                }
             }
             if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(dynamic LDS)");
         }
     } else {
+        if (b.fuse > 1) return fail(TEUK_EINVAL, "the segment sweep takes one step per launch");
         b.nt = maxnth <= 64 ? 64 : (maxnth <= 128 ? 128 : 256);
         if (b.nt_req > b.nt) b.nt = b.nt_req;
         if (b.nt > 256) return fail(TEUK_EINVAL, "the segment sweep takes blocks of at most 256 threads");
@@ -499,12 +517,19 @@ int do_steps(Batch &b, long n) {
     int cur = b.inst[0].cur;
     long left = n;
     hipError_t e = hipSuccess;
-    if (b.graph_steps > 0 && left >= b.graph_steps) {
+    // a launch advances `fuse` steps (the remainder goes one step per launch);
+    // a captured graph holds about graph_steps / fuse launches, an even number
+    // of them, so that every replay starts from the buffer it was captured on
+    const int F = b.fuse;
+    int glaunches = b.graph_steps / F;
+    if (b.graph_steps > 0 && glaunches % 2) glaunches = glaunches > 1 ? glaunches - 1 : 2;
+    const int gsteps = glaunches * F;
+    if (glaunches > 0 && left >= gsteps) {
         if (!b.gexec || b.graph_parity != cur) {
             drop_graph(b);
             e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                for (int q = 0; q < b.graph_steps && e == hipSuccess; ++q) e = step_launch(b, (cur + q) & 1);
+                for (int q = 0; q < glaunches && e == hipSuccess; ++q) e = step_launch(b, (cur + q) & 1, F);
                 hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
                 if (e == hipSuccess) e = e2;
             }
@@ -516,14 +541,18 @@ int do_steps(Batch &b, long n) {
             }
             b.graph_parity = cur;
         }
-        while (left >= b.graph_steps && e == hipSuccess) {
+        while (left >= gsteps && e == hipSuccess) {
             e = hipGraphLaunch(b.gexec, b.stream);
-            left -= b.graph_steps;
-            cur = (cur + b.graph_steps) & 1;
+            left -= gsteps;
+            cur = (cur + glaunches) & 1;
         }
     }
+    for (; left >= F && e == hipSuccess; left -= F) {
+        e = step_launch(b, cur, F);
+        cur ^= 1;
+    }
     for (; left > 0 && e == hipSuccess; --left) {
-        e = step_launch(b, cur);
+        e = step_launch(b, cur, 1);
         cur ^= 1;
     }
     if (e != hipSuccess) {
@@ -686,6 +715,30 @@ int teuk_batch_set_sweep(teuk_batch_t *b, int sweep) {
     return set_sweep(b->b, sweep);
 }
 int teuk_get_sweep(const teuk_t *h) { return h ? h->b.sweep : TEUK_EINVAL; }
+
+static int set_fuse(Batch &b, int ns) {
+    if (ns != 1 && ns != 2 && ns != 4) return fail(TEUK_EINVAL, "steps per launch must be 1, 2 or 4");
+    if (int rc = check_ok(b)) return rc;
+    hipStreamSynchronize(b.stream);
+    const int old = b.fuse;
+    b.fuse = ns;
+    int rc = build_worklist(b);
+    if (rc != TEUK_OK) {
+        b.fuse = old;
+        const std::string msg = g_err;
+        build_worklist(b);
+        return fail(rc, msg);
+    }
+    return TEUK_OK;
+}
+int teuk_set_fuse(teuk_t *h, int steps_per_launch) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_fuse(h->b, steps_per_launch);
+}
+int teuk_batch_set_fuse(teuk_batch_t *b, int steps_per_launch) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_fuse(b->b, steps_per_launch);
+}
 
 int teuk_set_launch(teuk_t *h, int segcols, int block) {
     if (!h) return fail(TEUK_EINVAL, "handle is NULL");

@@ -58,6 +58,8 @@ _SIGS = {
     "teuk_set_sweep": ([_P, ctypes.c_int], ctypes.c_int),
     "teuk_get_sweep": ([_P], ctypes.c_int),
     "teuk_batch_set_sweep": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_set_fuse": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_batch_set_fuse": ([_P, ctypes.c_int], ctypes.c_int),
     "teuk_get_coefficients": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "teuk_set_coefficients": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "teuk_batch_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _D,
@@ -181,6 +183,9 @@ class Teuk:
     def sweep(self):
         return lib().teuk_get_sweep(self.h)
 
+    def set_fuse(self, steps_per_launch):
+        _check(lib().teuk_set_fuse(self.h, int(steps_per_launch)))
+
     def check_finite(self):
         ok = ctypes.c_int(0)
         rc = lib().teuk_check_finite(self.h, ctypes.byref(ok))
@@ -259,6 +264,9 @@ class TeukBatch:
 
     def set_sweep(self, sweep):
         _check(lib().teuk_batch_set_sweep(self.h, int(sweep)))
+
+    def set_fuse(self, steps_per_launch):
+        _check(lib().teuk_batch_set_fuse(self.h, int(steps_per_launch)))
 
     def use_graph(self, k):
         _check(lib().teuk_batch_use_graph(self.h, int(k)))

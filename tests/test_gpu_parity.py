@@ -182,6 +182,73 @@ def test_largest_theta_grid(words):
             assert np.array_equal(got[f], other[f]), (sweep, f)
 
 
+# (words, n_theta, block, segcols, steps per launch): blocks at both radial
+# boundaries, ragged last segments, step counts that leave a remainder
+FUSED = [(1, 32, 256, 4, 4), (1, 32, 256, 9, 2), (1, 64, 512, 4, 4), (1, 64, 512, 10, 2),
+         (2, 32, 256, 4, 4), (2, 32, 512, 12, 2), (2, 64, 512, 3, 4)]
+
+
+@pytest.mark.parametrize("words,nth,block,seg,fuse", FUSED, ids=["w%d-t%d-b%d-s%d-f%d" % c for c in FUSED])
+def test_fused_steps_are_bitwise(words, nth, block, seg, fuse):
+    """Several steps per launch give the same bits as one step per launch, with
+    and without graph replay, and match the oracle."""
+    w = inputs.C1.with_(n_r=47, n_theta=nth, rstar_min=60.0, rstar_max=150.0, words=words, m=1, a_over_M=0.8)
+    fields = inputs.initial_fields(w)
+    _note("fused words=%d n_theta=%d block=%d segcols=%d fuse=%d" % (words, nth, block, seg, fuse))
+    ref = _run_gpu(w, fields, 11, tile=seg, sweep=T.SWEEP_WIDE, block=block)
+    for graph in (0, 4):
+        h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), words)
+        h.set_sweep(T.SWEEP_WIDE)
+        h.set_launch(seg, block)
+        h.set_fuse(fuse)
+        h.use_graph(graph)
+        h.set_initial(*fields)
+        h.step(11)
+        got = h.fields()
+        assert h.steps_done == 11
+        h.close()
+        for f in range(4):
+            assert np.array_equal(got[f], ref[f]), (graph, f)
+    assert rel_linf(ref, oracle_run(w, fields, 11)) <= TOL[words]
+
+
+def test_fused_batch_equals_single():
+    ws = [inputs.C1.with_(n_r=30 + 11 * k, n_theta=32, rstar_min=60.0, rstar_max=150.0, m=k, a_over_M=0.3 * k,
+                          words=2, seed=k) for k in range(3)]
+    b = T.TeukBatch([(w.s, w.m, w.a_over_M, _grid(w)) for w in ws], 2)
+    b.set_sweep(T.SWEEP_WIDE)
+    b.set_launch(4, 256)
+    b.set_fuse(4)
+    fields = [inputs.initial_fields(w) for w in ws]
+    for k, f in enumerate(fields):
+        b.set_initial(k, *f)
+    b.step(9)
+    for k, w in enumerate(ws):
+        single = _run_gpu(w, fields[k], 9, tile=4, sweep=T.SWEEP_WIDE, block=256)
+        for f in range(4):
+            assert np.array_equal(b.read_field(k, f), single[f]), (k, f)
+    b.close()
+
+
+def test_fuse_rejects_unsupported_shapes():
+    w = inputs.C1.with_(n_r=40, n_theta=32, words=4)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 4)
+    with pytest.raises(T.TeukError):
+        h.set_fuse(2)                       # quad-double has no fused form
+    with pytest.raises(T.TeukError):
+        h.set_fuse(3)
+    h.close()
+    w = inputs.C1.with_(n_r=40, n_theta=32, words=1)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 1)
+    h.set_sweep(T.SWEEP_WIDE)
+    h.set_launch(40, 256)
+    with pytest.raises(T.TeukError):
+        h.set_fuse(4)                       # 40 + 12 columns need more than two iterations
+    h.set_launch(4, 256)
+    h.set_fuse(4)                           # the previous failure left the handle usable
+    h.close()
+
+
 def test_wide2_rejected_for_multiword():
     w = inputs.C1.with_(n_r=20, n_theta=8, words=2)
     h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 2)
@@ -231,6 +298,11 @@ def test_checkpoint_restart_and_graph_are_bitwise():
     h.set_initial(*fields)
     h.use_graph(4)
     h.step(10)                    # 2 graph replays + 2 plain launches
+    for f in range(4):
+        assert np.array_equal(h.read_field(f), full[f])
+    h.set_initial(*fields)
+    h.use_graph(3)                # an odd graph length is rounded to an even launch count
+    h.step(10)
     for f in range(4):
         assert np.array_equal(h.read_field(f), full[f])
     h.close()

@@ -138,5 +138,7 @@ def test_null_arguments_are_rejected():
     assert L.teuk_set_sweep(None, 1) == T.TEUK_EINVAL
     assert L.teuk_batch_set_sweep(None, 1) == T.TEUK_EINVAL
     assert L.teuk_get_sweep(None) == T.TEUK_EINVAL
+    assert L.teuk_set_fuse(None, 2) == T.TEUK_EINVAL
+    assert L.teuk_batch_set_fuse(None, 2) == T.TEUK_EINVAL
     assert L.teuk_destroy(None) == T.TEUK_OK
     assert L.teuk_arith_host(3, 0, None, None, None, 1) == T.TEUK_EINVAL
