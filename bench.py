@@ -26,11 +26,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # and WRITE_SIZE runs of paper_1006_0663_amd/profile_step.py (the summary under
 # profiles/ gives the commands).  FETCH_SIZE reads 131,093 KiB for a 256 MiB
 # device copy (scale 2.0), WRITE_SIZE 262,144 KiB (scale 1.0).  Valid only for
-# the launch shape and kernel sources they were taken with: `source` is
+# the launch shapes and kernel sources they were taken with: `source` is
 # kernel_source_digest() at that time; otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "shape": (2, 4, 128), "source": "f9e0cab04282",
-    "fetch_kib": 9426.8, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0,
+    "source": "e61ecaaf2706", "fetch_scale": 2.0, "write_scale": 1.0,
+    # (sweep, segcols, block, steps per launch): (FETCH_SIZE, WRITE_SIZE) KiB per launch
+    "per_shape": {(2, 4, 128, 1): (9429.2, 16384.0), (1, 4, 256, 1): (9380.7, 16384.0),
+                  (1, 8, 512, 1): (9373.7, 16384.0), (1, 6, 512, 1): (9363.2, 16384.0)},
 }
 
 
@@ -56,16 +58,16 @@ def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=Non
     h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
     h.set_stream(stream.cuda_stream)
     h.set_initial(*fields)
+    if graph:
+        h.use_graph(graph)          # before tuning: candidates are timed as they will run
     if fixed_shape:
         autotune.apply(h, fixed_shape)
-        shape = tuple(fixed_shape)
+        shape = tuple(fixed_shape) + (1,) * (4 - len(fixed_shape))
     elif tile:
         h.set_launch(tile, 0)
-        shape = (h.sweep, tile, 0)
+        shape = (h.sweep, tile, 0, 1)
     else:
-        shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)[:3]
-    if graph:
-        h.use_graph(graph)
+        shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream, steps=max(20, 2 * graph))[:4]
     h.set_initial(*fields)
     with torch.cuda.stream(stream):
         h.step(warmup)
@@ -122,7 +124,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--graph", type=int, default=100, help="steps per captured HIP graph (0 = plain launches)")
     ap.add_argument("--tile", type=int, default=0, help="r* nodes per segment (0 = library default)")
-    ap.add_argument("--shape", default="", help="headline launch shape 'sweep,segcols,block' (default: autotuned)")
+    ap.add_argument("--shape", default="", help="headline launch shape 'sweep,segcols,block[,fuse]' (default: autotuned)")
     ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=32)
@@ -156,8 +158,9 @@ def main():
     fpu = opcount.flops_per_update(1)
     traffic = traffic_bytes = None
     m = MEASURED_TRAFFIC
-    if tuple(shape) == m["shape"] and kernel_source_digest() == m["source"]:
-        traffic_bytes = 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+    kib = m["per_shape"].get(tuple(shape)) if kernel_source_digest() == m["source"] else None
+    if kib:
+        traffic_bytes = 1024.0 * (kib[0] * m["fetch_scale"] + kib[1] * m["write_scale"])
         traffic = traffic_bytes / (ms_step / 1e3) / 1e9
     out = {
         "metric": "grid-point updates/sec per precision (FP64/dd/qd) + % FP64 peak; batched vs plain",
@@ -167,7 +170,8 @@ def main():
         "config": {"workload": "teukolsky-lw fp64 s=-2 m=2 a/M=0.9 4096x128 r*[-200,800] cfl=%g steps=%d"
                                % (w.cfl, w.steps),
                    "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph,
-                   "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1], "block": shape[2]},
+                   "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1], "block": shape[2],
+                   "steps_per_launch": shape[3]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_bytes,
@@ -191,7 +195,7 @@ def main():
             f = opcount.flops_per_update(wx.words)
             per[wx.name] = {"words": wx.words, "steps": wx.steps, "updates_per_s": ups,
                             "ms_per_step": msx / wx.steps, "sweep": ["segment", "wide", "wide2"][shp[0]],
-                            "segcols": shp[1], "block": shp[2],
+                            "segcols": shp[1], "block": shp[2], "steps_per_launch": shp[3],
                             "fp64_flops_per_update": f,
                             "pct_fp64_peak": 100.0 * f * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
                             "hbm_GBs_algorithmic": opcount.bytes_per_update(wx.words) * ups / 1e9,
@@ -217,9 +221,9 @@ def bench_batched(T, inputs, args, torch, stream, log):
         b.set_initial(k, *f)
     if args.tile:
         b.set_launch(args.tile, 0)
-        bshape = (-1, args.tile, 0)
+        bshape = (-1, args.tile, 0, 1)
     else:
-        bshape = autotune.tune(b, 2, [(w.n_r, w.n_theta) for w in ws], torch, stream, steps=5)[:3]
+        bshape = autotune.tune(b, 2, [(w.n_r, w.n_theta) for w in ws], torch, stream, steps=8)[:4]
     if args.graph:
         b.use_graph(args.graph)
     for k, f in enumerate(fields):
@@ -244,7 +248,7 @@ def bench_batched(T, inputs, args, torch, stream, log):
         if args.tile:
             h.set_launch(args.tile, 0)
         else:
-            autotune.tune(h, 2, [(w.n_r, w.n_theta)], torch, stream, steps=5)
+            autotune.tune(h, 2, [(w.n_r, w.n_theta)], torch, stream, steps=8)
         if args.graph:
             h.use_graph(args.graph)
         h.set_initial(*f)
@@ -267,7 +271,7 @@ def bench_batched(T, inputs, args, torch, stream, log):
     return {"instances": len(ws), "steps": steps, "points": pts, "words": 2,
             "batched_updates_per_s": ub,
             "plain_loop_updates_per_s": pts * steps / (ms_p / 1e3),
-            "speedup": ms_p / ms_b, "sweep": bshape[0], "segcols": bshape[1], "block": bshape[2],
+            "speedup": ms_p / ms_b, "sweep": bshape[0], "segcols": bshape[1], "block": bshape[2], "steps_per_launch": bshape[3],
             "batched_pct_fp64_peak": 100.0 * f * ub / (FP64_VECTOR_PEAK_TFLOPS * 1e12)}
 
 

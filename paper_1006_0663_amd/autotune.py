@@ -1,7 +1,7 @@
 """Autotuner for the step kernel's launch shape.
 
-Times a short run of every candidate (sweep, segment length, block size) on
-the actual instance or batch with HIP events on the handle's stream, keeps
+Times a short run of every candidate (sweep, segment length, block size,
+steps per launch) on the actual instance or batch with HIP events on the handle's stream, keeps
 the fastest, and caches the choice in a JSON file keyed by device, precision
 and grid shape (``TEUK_TUNE_CACHE``, default tune_cache.json next to this
 file).  The launch shape does not change results (tested bitwise), only speed.
@@ -11,13 +11,18 @@ import os
 
 SEGMENT, WIDE, WIDE2 = 0, 1, 2
 
-# (sweep, segcols, block) per precision (words); block 0 = library default
+# (sweep, segcols, block, steps per launch) per precision (words); block 0 =
+# library default.  Fused launches (2 or 4 steps) pay off on small grids,
+# where one step does not fill the chip and launch overhead dominates.
 CANDIDATES = {
-    1: [(WIDE, s, b) for b in (128, 256, 512) for s in (4, 6, 8, 12, 16, 24)]
-       + [(WIDE2, s, b) for b in (128, 256, 512) for s in (4, 6, 8, 10, 16, 22)]
-       + [(SEGMENT, 4, 256), (SEGMENT, 8, 256)],
-    2: [(WIDE, s, b) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12)] + [(SEGMENT, 2, 0), (SEGMENT, 2, 128)],
-    4: [(WIDE, s, b) for b in (128, 256) for s in (2, 4, 6, 8, 12)] + [(SEGMENT, 2, 128), (SEGMENT, 2, 0)],
+    1: [(WIDE, s, b, 1) for b in (128, 256, 512) for s in (4, 6, 8, 12, 16, 24)]
+       + [(WIDE2, s, b, 1) for b in (128, 256, 512) for s in (4, 6, 8, 10, 16, 22)]
+       + [(SEGMENT, 4, 256, 1), (SEGMENT, 8, 256, 1)]
+       + [(WIDE, s, b, f) for f in (2, 4) for b in (256, 512) for s in (2, 4)],
+    2: [(WIDE, s, b, 1) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12)]
+       + [(SEGMENT, 2, 0, 1), (SEGMENT, 2, 128, 1)]
+       + [(WIDE, s, b, 2) for b in (256, 512) for s in (2, 4)],
+    4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)],
 }
 
 
@@ -53,26 +58,33 @@ def candidates(words, max_nth):
 
 
 def apply(handle, shape):
-    sweep, segcols, block = shape
+    """shape: (sweep, segcols, block[, steps per launch])."""
+    sweep, segcols, block = shape[:3]
+    fuse = shape[3] if len(shape) > 3 else 1
+    handle.set_fuse(1)               # single steps: every sweep and shape accepts them
     handle.set_launch(1, 0)          # a shape every sweep accepts
     handle.set_sweep(sweep)
     handle.set_launch(segcols, block)
+    handle.set_fuse(fuse)
 
 
-def tune(handle, words, shapes, torch, stream, steps=20, reps=2, use_cache=True, log=None):
-    """Pick the fastest (sweep, segcols, block) for `handle` (Teuk or TeukBatch,
-    already holding valid fields and set to `stream`), leave the handle set to
-    it and return (sweep, segcols, block, us_per_step)."""
+def tune(handle, words, shapes, torch, stream, steps=20, reps=3, use_cache=True, log=None):
+    """Pick the fastest (sweep, segcols, block, fuse) for `handle` (Teuk or
+    TeukBatch, already holding valid fields and set to `stream`), leave the
+    handle set to it and return (sweep, segcols, block, fuse, us_per_step)."""
     from paper_1006_0663_amd.teuk import TeukError
     dev = torch.cuda.get_device_name(0)
     k = key(dev, words, shapes)
     db = _load() if use_cache else {}
-    if k in db and len(db[k]) == 4:
+    if k in db and len(db[k]) == 5:
         best = tuple(db[k])
-        apply(handle, best[:3])
+        apply(handle, best[:4])
         return best
     best = None
     max_nth = max(n for _, n in shapes)
+    with torch.cuda.stream(stream):
+        handle.step(10 * steps)          # bring the clocks up before the first candidate
+        stream.synchronize()
     for cand in candidates(words, max_nth):
         try:
             apply(handle, cand)
@@ -81,7 +93,7 @@ def tune(handle, words, shapes, torch, stream, steps=20, reps=2, use_cache=True,
                 log("tune %s: %s skipped (%s)" % (k, cand, ex))
             continue
         with torch.cuda.stream(stream):
-            handle.step(2)
+            handle.step(4)
             times = []
             for _ in range(reps):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -92,10 +104,10 @@ def tune(handle, words, shapes, torch, stream, steps=20, reps=2, use_cache=True,
                 times.append(e0.elapsed_time(e1) * 1e3 / steps)
         t = min(times)
         if log:
-            log("tune %s: sweep=%d segcols=%d block=%d %.2f us/step" % (k, cand[0], cand[1], cand[2], t))
-        if best is None or t < best[3]:
-            best = (cand[0], cand[1], cand[2], t)
-    apply(handle, best[:3])
+            log("tune %s: sweep=%d segcols=%d block=%d fuse=%d %.2f us/step" % ((k,) + tuple(cand) + (t,)))
+        if best is None or t < best[4]:
+            best = tuple(cand) + (t,)
+    apply(handle, best[:4])
     if use_cache:
         db = _load()
         db[k] = list(best)

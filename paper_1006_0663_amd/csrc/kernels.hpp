@@ -975,7 +975,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
             const cx<T> lh_m = xget<T>(XLH + sk * CH * nth, nth, jj);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                const int kp = k0p + p, i = as + kp - 1;
+                const int kp = k0p + p, i = (NS == 1 ? a : as) + kp - 1;
                 const bool on = lane_on && kp >= 2 && kp < K;
                 // (FP64 computes on every lane; the multiword types skip whole
                 // wavefronts with nothing to do, which saves far more there)
@@ -988,10 +988,12 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                     coef(false, ic, cf);
                     un = lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
                 }
-                if (last) {
+                if constexpr (NS == 1) {
+                    if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
+                } else if (last) {
                     // nodes of the segment, radial boundary excluded
                     if (lane_on && i >= max(c0, 1) && i < min(c1, nr - 1)) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
-                } else if constexpr (NS > 1) {
+                } else {
                     u_out[p] = (i == 0 || i == nr - 1) ? zero : un;
                 }
             }
@@ -1011,7 +1013,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 // stage 1 (lw1) at half node a + k - 1/2 (half index a + k - 1)
-                const int k = k0 + p, h = as + k - 1;
+                const int k = k0 + p, h = (NS == 1 ? a : as) + k - 1;
                 const bool on = lane_on && k >= 1 && k < K;
                 uh[p] = zero;
                 if (W > 1 && !on) continue;
@@ -1044,14 +1046,20 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     if constexpr (TM > 0) {
         // every column of the lane was requested up front (above): one memory
         // latency per launch instead of one per iteration
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
+        if constexpr (NS == 1) {
 #pragma unroll
             for (int t = 0; t <= TM; ++t)
-                if (!iteration(t, ua[t < TM ? t : TM - 1], ua[t > 0 ? t - 1 : 0], st == NS - 1)) break;
-            k0 = g * P;                             // next step: same lanes, same slots,
-            sk = lane_on ? g : 0;                   // columns one node further left
-            --as;
+                if (!iteration(t, ua[t < TM ? t : TM - 1], nullptr, true)) break;
+        } else {
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+#pragma unroll
+                for (int t = 0; t <= TM; ++t)
+                    if (!iteration(t, ua[t < TM ? t : TM - 1], ua[t > 0 ? t - 1 : 0], st == NS - 1)) break;
+                k0 = g * P;                         // next step: same lanes, same slots,
+                sk = lane_on ? g : 0;               // columns one node further left
+                --as;
+            }
         }
     } else {
         Pt<T> u_next[P];

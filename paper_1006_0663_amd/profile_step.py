@@ -23,6 +23,7 @@ def main():
     ap.add_argument("--segcols", type=int, default=4)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--sweep", type=int, default=-1, help="0 segment, 1 wide, 2 wide with runs of two, -1 default")
+    ap.add_argument("--fuse", type=int, default=1, help="steps per launch (1, 2 or 4)")
     ap.add_argument("--tuned", action="store_true", help="use the autotuner's shape (cached if tuned before)")
     a = ap.parse_args()
     w = inputs.WORKLOADS[a.workload]
@@ -38,16 +39,17 @@ def main():
         from paper_1006_0663_amd import autotune
         stream = torch.cuda.current_stream()
         h.set_stream(stream.cuda_stream)
-        a.sweep, a.segcols, a.block, _ = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)
+        a.sweep, a.segcols, a.block, a.fuse, _ = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream)
         h.set_initial(*inputs.initial_fields(w))
     else:
         h.set_sweep(a.sweep)
         h.set_launch(a.segcols, a.block)
+        h.set_fuse(a.fuse)
     h.step(a.steps)
     ok = h.check_finite()
     h.close()
-    print("profile_step: %s %d steps sweep=%d segcols=%d block=%d finite=%s copy=%d MiB"
-          % (w.name, a.steps, a.sweep, a.segcols, a.block, ok, COPY_MIB), flush=True)
+    print("profile_step: %s %d steps sweep=%d segcols=%d block=%d fuse=%d finite=%s copy=%d MiB"
+          % (w.name, a.steps, a.sweep, a.segcols, a.block, a.fuse, ok, COPY_MIB), flush=True)
     return 0 if ok else 1
 
 

@@ -87,6 +87,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libteuk.so is not built (run __graft_entry__.build()); "
                                "there is no fallback implementation")
+        # PyTorch ships its own HIP runtime under a different file name; loaded
+        # first, it also serves this library (same soname), so the process holds
+        # one runtime and torch's streams and device pointers are valid here.
+        # Loaded after this library, torch would start a second runtime that
+        # finds no GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)

@@ -230,6 +230,32 @@ def test_fused_batch_equals_single():
     b.close()
 
 
+@pytest.mark.parametrize("words", [1, 2])
+def test_autotuned_shape_is_bitwise(words, tmp_path, monkeypatch):
+    """The autotuner (fused candidates included) leaves the handle on a shape
+    that gives the same bits as the default launch."""
+    import torch
+    from paper_1006_0663_amd import autotune
+    monkeypatch.setenv("TEUK_TUNE_CACHE", str(tmp_path / "cache.json"))
+    w = inputs.C1.with_(n_r=47, n_theta=32, rstar_min=60.0, rstar_max=150.0, words=words, m=1, a_over_M=0.8)
+    fields = inputs.initial_fields(w)
+    ref = _run_gpu(w, fields, 11)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), words)
+    h.set_stream(stream.cuda_stream)
+    h.set_initial(*fields)
+    best = autotune.tune(h, words, [(w.n_r, w.n_theta)], torch, stream, steps=8, reps=1)
+    _note("autotuned words=%d: %s" % (words, best))
+    assert len(best) == 5 and best[3] in (1, 2, 4)
+    h.set_initial(*fields)
+    h.step(11)
+    got = h.fields()
+    h.close()
+    for f in range(4):
+        assert np.array_equal(got[f], ref[f]), f
+
+
 def test_fuse_rejects_unsupported_shapes():
     w = inputs.C1.with_(n_r=40, n_theta=32, words=4)
     h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 4)
