@@ -190,7 +190,9 @@ hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev 
                          int nitems, int parity, hipStream_t stream, bool attr_only) {
     constexpr int W = words_of<T>::value;
     constexpr bool has_one = W == 1;
-    constexpr bool fused = TM >= 1 && TM <= 2 && P == 1 && (W == 2 || (W == 1 && CM > 0));
+    // fused forms: runs of one column, one or two unrolled iterations (FP64:
+    // up to four for two steps per launch)
+    constexpr bool fused = TM >= 1 && TM <= (W == 1 ? 4 : 2) && P == 1 && (W == 2 || (W == 1 && CM > 0));
     const bool o = has_one && one;
     if (ns == 1) {
         if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 1>(lds, one, insts, items, nitems, parity, stream, attr_only);
@@ -201,7 +203,7 @@ hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev 
             if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
             return wide_launch_one<T, NT, P, CM, TM, false, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
         }
-        if (ns == 4) {
+        if (ns == 4 && TM <= 2) {
             if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
             return wide_launch_one<T, NT, P, CM, TM, false, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
         }

@@ -226,6 +226,15 @@ void xcd_order(std::vector<lwk::WorkItem> &items, size_t first, size_t n) {
     }
 }
 
+// Columns the wide-sweep work item [c0, c1) of a grid of nr nodes holds with
+// ns steps per launch: ns neighbours on each side (fewer at the domain
+// boundaries) and, when it reaches the right boundary with ns > 1, ns padding
+// columns past it (the step kernel computes the same count).
+int wide_cols(int c0, int c1, int nr, int ns) {
+    const int a = std::max(c0 - ns, 0), e = std::min(c1 - 1 + ns, nr - 1);
+    return e - a + 1 + ((ns > 1 && e == nr - 1) ? ns : 0);
+}
+
 // (Re)build descriptors and the work list; all instances must share `cur`.
 int build_worklist(Batch &b) {
     int maxnth = 0;
@@ -275,18 +284,22 @@ int build_worklist(Batch &b) {
         // past the right domain boundary)
         int ti = 0;
         for (auto &I : b.inst) {
-            const int K = std::min(b.segcols, I.g.n_r) + 2 * b.fuse + (b.fuse > 1 ? b.fuse : 0);
-            const int per = (b.nt / I.g.n_theta) * wide_run(b.sweep);
-            ti = std::max(ti, (K + per - 1) / per);
+            const int nr = I.g.n_r, per = (b.nt / I.g.n_theta) * wide_run(b.sweep);
+            for (int c0 = 0; c0 < nr; c0 += b.segcols) {
+                const int K = wide_cols(c0, std::min(c0 + b.segcols, nr), nr, b.fuse);
+                ti = std::max(ti, (K + per - 1) / per);
+            }
         }
         b.tm = ti <= 4 ? ti : 0;
         if (b.fuse > 1) {
-            const bool ok = b.tm >= 1 && b.tm <= 2 && wide_run(b.sweep) == 1 && b.nt >= 128 && b.nt <= 512 &&
+            const int max_tm = b.words == 1 && b.fuse == 2 ? 4 : 2;
+            const bool ok = b.tm >= 1 && b.tm <= max_tm && wide_run(b.sweep) == 1 && b.nt >= 128 && b.nt <= 512 &&
                             (b.words == 2 || (b.words == 1 && b.cmode > 0));
             if (!ok)
                 return fail(TEUK_EINVAL, "fused steps need dd or FP64 per-point coefficients, runs of one column, "
-                                         "blocks of 128-512 threads and at most two iterations per step "
-                                         "(segcols + 3 * fuse <= 2 * block / n_theta)");
+                                         "blocks of 128-512 threads and at most two iterations per step (FP64 "
+                                         "with two steps per launch: four), i.e. segcols + 2 * fuse columns "
+                                         "(+ fuse at the right boundary) within iterations * block / n_theta");
         }
         if (b.lds > 64 * 1024) {
             const int run = wide_run(b.sweep);

@@ -184,7 +184,12 @@ def test_largest_theta_grid(words):
 
 # (words, n_theta, block, segcols, steps per launch): blocks at both radial
 # boundaries, ragged last segments, step counts that leave a remainder
+# (words, n_theta, block, segcols, steps per launch); the FP64 two-step cases
+# with 64 and 128 theta rows take three or four unrolled iterations, the last
+# one with a one-column last segment (the second-to-last block reaches the
+# right boundary)
 FUSED = [(1, 32, 256, 4, 4), (1, 32, 256, 9, 2), (1, 64, 512, 4, 4), (1, 64, 512, 10, 2),
+         (1, 64, 256, 8, 2), (1, 64, 256, 12, 2), (1, 128, 512, 8, 2), (1, 64, 512, 23, 2),
          (2, 32, 256, 4, 4), (2, 32, 512, 12, 2), (2, 64, 512, 3, 4)]
 
 
