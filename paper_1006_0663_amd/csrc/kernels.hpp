@@ -435,6 +435,47 @@ MPA Pt<T> lw_stage(const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d, const cx
     return o;
 }
 
+// FP64 stage with the coefficients built from the radial row rr at the point
+// (the per-point coefficient modes): the terms of coef_fp64_point followed by
+// lw_stage, except that q = 1/X, a factor of every Pi-row coefficient but B,
+// multiplies their sum once instead of each coefficient (seven products fewer
+// per stage, two more).  Writing K = q (kr + i ki), C_t = q (ST1 + i ci),
+// W = q SD, C0 = q (ST4 + i ST5):
+//   out_Pi = base_Pi + B dPi + q (-(kr + i ki) dPhi + SD Lbar + (ST4 + i ST5) Phibar
+//                                 - (ST1 + i ci) Pibar)
+template <class RowPtr>
+MPA Pt<double> lw_stage_row(const Pt<double> &base, const Pt<double> &bar, const Pt<double> &d,
+                            const cx<double> &lbar, RowPtr rr, double cs, double s2, double s) {
+    const double X = rr[kVp2] - rr[kA2D] * s2;
+    const double rq = rsqrt_nr(X);
+    const double q = rq * rq;
+    const double b = rr[kVp] * rq;
+    const double B = rr[kSIVp] * rq;
+    const double kr = fma(s2 * q, rr[kSIT8], -(b * rr[kSIT1] + rr[kSIT6]));
+    const double ki = -fma(b, cs * rr[kSIT3] + rr[kSIT2], rr[kSIT7]);
+    const double ci = cs * rr[kST3] + rr[kST2];
+    Pt<double> o;
+    o.phi.re = fma(s, bar.pi.re, fma(-B, d.phi.re, base.phi.re));
+    o.phi.im = fma(s, bar.pi.im, fma(-B, d.phi.im, base.phi.im));
+    double sr = -kr * d.phi.re;
+    sr = fma(ki, d.phi.im, sr);
+    sr = fma(rr[kSD], lbar.re, sr);
+    sr = fma(rr[kST4], bar.phi.re, sr);
+    sr = fma(-rr[kST5], bar.phi.im, sr);
+    sr = fma(-rr[kST1], bar.pi.re, sr);
+    sr = fma(ci, bar.pi.im, sr);
+    double si = -kr * d.phi.im;
+    si = fma(-ki, d.phi.re, si);
+    si = fma(rr[kSD], lbar.im, si);
+    si = fma(rr[kST4], bar.phi.im, si);
+    si = fma(rr[kST5], bar.phi.re, si);
+    si = fma(-rr[kST1], bar.pi.im, si);
+    si = fma(-ci, bar.pi.re, si);
+    o.pi.re = fma(q, sr, fma(B, d.pi.re, base.pi.re));
+    o.pi.im = fma(q, si, fma(B, d.pi.im, base.pi.im));
+    return o;
+}
+
 template <class T>
 MPA Pt<T> ld_pt(const double *u, size_t plane, size_t idx) {
     constexpr int W = words_of<T>::value;
@@ -571,6 +612,21 @@ __device__ __forceinline__ void load_coef(const GLB double *planes, const double
     }
 }
 
+// one stage at node/half node idx: coefficients from the stored planes, or
+// (FP64 per-point mode, ONFLY) the radial row staged in LDS
+template <class T, bool ONFLY>
+__device__ __forceinline__ Pt<T> stage_at(const GLB double *planes, const double *lrow, uint32_t plane,
+                                          uint32_t idx, double cs, double s2, const Pt<T> &base, const Pt<T> &bar,
+                                          const Pt<T> &d, const cx<T> &lbar, const T &s) {
+    if constexpr (words_of<T>::value == 1 && ONFLY) {
+        return lw_stage_row(base, bar, d, lbar, lrow, cs, s2, s);
+    } else {
+        T c[8];
+        load_coef<T, false>(planes, lrow, plane, idx, cs, s2, c);
+        return lw_stage(base, bar, d, lbar, c, s);
+    }
+}
+
 // LDS bytes the FP64 per-point mode needs for a block of NT threads
 MPA size_t rows_lds_bytes(int nt, int nth, int segcols) {
     const int G = nt / nth;
@@ -702,27 +758,24 @@ __global__ __launch_bounds__(NT) LWK_STEP_OCC void lw_step_kernel(const InstDev 
         __syncthreads();
         const cx<T> l_c = theta_stencil<T>(xp + gbase, NT, j, nth, R, wtab, wreg, qrow);
         const cx<T> lh_m32 = theta_stencil<T>(xh + gbase, NT, j, nth, R, wtab, wreg, qrow);
-        T cf[8];
         if (k >= 3) {
             // (lw2) at node c-2; indices are clamped so inactive lanes read valid memory
             const int i = c - 2;
             const bool on = seg_on && i <= e - 1;
             const int ic = min(max(i, 1), nr - 2);
-            load_coef<T, ONFLY>(gptr(I.cf), lrow_f + min(max(i - bnA, 0), bnB - bnA) * kRadRow, plane,
-                                (uint32_t)(ic * nth + j), cs_j, s2_j, cf);
-            const Pt<T> un = lw_stage(u_m2, pt_avg(uh_m52, uh_m32), pt_diff(uh_m52, uh_m32), c_avg(lh_m52, lh_m32),
-                                      cf, dt);
+            const Pt<T> un = stage_at<T, ONFLY>(gptr(I.cf), lrow_f + min(max(i - bnA, 0), bnB - bnA) * kRadRow, plane,
+                                                (uint32_t)(ic * nth + j), cs_j, s2_j, u_m2, pt_avg(uh_m52, uh_m32),
+                                                pt_diff(uh_m52, uh_m32), c_avg(lh_m52, lh_m32), dt);
             if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
         }
         Pt<T> uh_new = zero;
         if (k >= 1) {
             // (lw1) at half node c-1/2 (index c-1)
-            const bool on = seg_on && c <= e;
             const int hc = min(max(c - 1, 0), nr - 2);
-            load_coef<T, ONFLY>(gptr(I.ch), lrow_h + min(max(c - 1 - bnA, 0), bnB - bnA - 1) * kRadRow, hplane,
-                                (uint32_t)(hc * nth + j), cs_j, s2_j, cf);
             const Pt<T> bar = pt_avg(u_m1, u_c);
-            uh_new = lw_stage(bar, bar, pt_diff(u_m1, u_c), c_avg(l_m1, l_c), cf, hdt);
+            uh_new = stage_at<T, ONFLY>(gptr(I.ch), lrow_h + min(max(c - 1 - bnA, 0), bnB - bnA - 1) * kRadRow,
+                                        hplane, (uint32_t)(hc * nth + j), cs_j, s2_j, bar, bar, pt_diff(u_m1, u_c),
+                                        c_avg(l_m1, l_c), hdt);
         }
         u_m2 = u_m1;
         u_m1 = u_c;
@@ -913,18 +966,23 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         cs_j = gptr(I.trig)[jj];
         s2_j = gptr(I.trig)[nth + jj];
     }
-    // eight coefficients at node (half = false) or half node i, row j
-    auto coef = [&](bool half, int i, T *cf) {
+    // one stage at node (half = false) or half node i, row j, with the
+    // coefficients of that point
+    auto stage = [&](bool half, int i, const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d, const cx<T> &lbar,
+                     const T &s) -> Pt<T> {
         if constexpr (W == 1 && CM == 2) {
             const int iu = __builtin_amdgcn_readfirstlane(i);
-            coef_fp64_point((const CNS double *)(half ? I.rh : I.rf) + iu * kRadRow, cs_j, s2_j, cf);
+            return lw_stage_row(base, bar, d, lbar, (const CNS double *)(half ? I.rh : I.rf) + iu * kRadRow, cs_j,
+                                s2_j, s);
         } else if constexpr (W == 1 && CM == 1) {
-            coef_fp64_point((half ? lrow_h : lrow_f) + (i - a) * kRadRow, cs_j, s2_j, cf);
+            return lw_stage_row(base, bar, d, lbar, (half ? lrow_h : lrow_f) + (i - a) * kRadRow, cs_j, s2_j, s);
         } else {
             const GLB double *pl = gptr(half ? I.ch : I.cf);
             const uint32_t pn = half ? hplane : plane;
+            T cf[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) cf[q] = gld<T>(pl + q * W * pn, pn, (uint32_t)(i * nth + jj));
+            return lw_stage(base, bar, d, lbar, cf, s);
         }
     };
     double wreg[2 * RM + 1];
@@ -942,6 +1000,10 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     }
 
     int k0 = g * P, sk = lane_on ? g : 0;           // first column of this lane's run and the run's slot
+    // the slot's offsets into the ghosted arrays (sk * SP) and the per-row
+    // arrays (sk * SN), stepped along with sk instead of multiplied out
+    const int SN = CH * nth, GSP = G * SP, GSN = G * SN;
+    int so = sk * SP, sn = sk * SN;
     Pt<T> u_l[P], uh_l[P];                          // stage-2 operands kept from the previous iteration:
     cx<T> lh_l[P];                                  // u^n left of each column, half steps, their L
 #pragma unroll
@@ -956,12 +1018,13 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     // global memory in the last step, else (fused steps) to u_out
     auto iteration = [&](int t, const Pt<T> *u_c, Pt<T> *u_out, bool last) -> bool {
         const int sl = sk == 0 ? G : sk - 1;        // slot of the run to the left
-        d2 *const xp = XP + sk * SP, *const xh = XH + sk * SP;
+        const int slo = sk == 0 ? GSP : so - SP, sln = sk == 0 ? GSN : sn - SN;
+        d2 *const xp = XP + so, *const xh = XH + so;
 #pragma unroll
         for (int p = 0; p < P; ++p)
             if (lane_on && k0 + p < K) xput_ghosted<T>(xp + p * CH * RS, RS, j, nth, u_c[p].phi);
         const bool last_on = lane_on && k0 + P - 1 < K;
-        if (last_on) xput<T>(XPI + sk * CH * nth, nth, j, u_c[P - 1].pi);
+        if (last_on) xput<T>(XPI + sn, nth, j, u_c[P - 1].pi);
         __syncthreads();                                                        // B1
         // FP64 stages run on every lane with clamped indices (results of idle
         // lanes and of columns outside the segment are discarded); only the
@@ -971,8 +1034,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
             const int k0p = k0 - G * P;
             Pt<T> uh_m;                             // half step left of that run
             uh_m.phi = xget<T>(xh + (P - 1) * CH * RS, RS, RM + jj);
-            uh_m.pi = xget<T>(XHI + sk * CH * nth, nth, jj);
-            const cx<T> lh_m = xget<T>(XLH + sk * CH * nth, nth, jj);
+            uh_m.pi = xget<T>(XHI + sn, nth, jj);
+            const cx<T> lh_m = xget<T>(XLH + sn, nth, jj);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int kp = k0p + p, i = (NS == 1 ? a : as) + kp - 1;
@@ -984,9 +1047,7 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                     const int ic = min(max(i, a), e);
                     const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
                     const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
-                    T cf[8];
-                    coef(false, ic, cf);
-                    un = lw_stage(u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), cf, dt);
+                    un = stage(false, ic, u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), dt);
                 }
                 if constexpr (NS == 1) {
                     if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
@@ -1002,14 +1063,14 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         cx<T> l_c[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) l_c[p] = stencil_ghosted<T>(xp + p * CH * RS, RS, jj, nth, R, wtab, wreg);
-        if (last_on) xput<T>(XL + sk * CH * nth, nth, j, l_c[P - 1]);
+        if (last_on) xput<T>(XL + sn, nth, j, l_c[P - 1]);
         Pt<T> u_m1;                                 // u^n left of the run
-        u_m1.phi = xget<T>(XP + sl * SP + (P - 1) * CH * RS, RS, RM + jj);
-        u_m1.pi = xget<T>(XPI + sl * CH * nth, nth, jj);
+        u_m1.phi = xget<T>(XP + slo + (P - 1) * CH * RS, RS, RM + jj);
+        u_m1.pi = xget<T>(XPI + sln, nth, jj);
         __syncthreads();                                                        // B2
         Pt<T> uh[P];
         {
-            const cx<T> l_m1 = xget<T>(XL + sl * CH * nth, nth, jj);
+            const cx<T> l_m1 = xget<T>(XL + sln, nth, jj);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 // stage 1 (lw1) at half node a + k - 1/2 (half index a + k - 1)
@@ -1020,19 +1081,17 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                 const int hc = min(max(h, a), e - 1);
                 const Pt<T> &ua = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
                 const cx<T> &la = p == 0 ? l_m1 : l_c[p > 0 ? p - 1 : 0];
-                T cf[8];
-                coef(true, hc, cf);
                 const Pt<T> bar = pt_avg(ua, u_c[p]);
-                uh[p] = lw_stage(bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), cf, hdt);
+                uh[p] = stage(true, hc, bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), hdt);
                 if (on) xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
             }
-            if (last_on && k0 + P - 1 >= 1) xput<T>(XHI + sk * CH * nth, nth, j, uh[P - 1].pi);
+            if (last_on && k0 + P - 1 >= 1) xput<T>(XHI + sn, nth, j, uh[P - 1].pi);
         }
         __syncthreads();                                                        // B3
         cx<T> lh[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) lh[p] = stencil_ghosted<T>(xh + p * CH * RS, RS, jj, nth, R, wtab, wreg);
-        if (last_on && k0 + P - 1 >= 1) xput<T>(XLH + sk * CH * nth, nth, j, lh[P - 1]);
+        if (last_on && k0 + P - 1 >= 1) xput<T>(XLH + sn, nth, j, lh[P - 1]);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             u_l[p] = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
@@ -1040,7 +1099,9 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
             lh_l[p] = lh[p];
         }
         k0 += G * P;
-        sk = sk == 0 ? G : sk - 1;                  // (kb + G) mod (G+1) == (kb - 1) mod (G+1)
+        sk = sl;                                    // (kb + G) mod (G+1) == (kb - 1) mod (G+1)
+        so = slo;
+        sn = sln;
         return true;
     };
     if constexpr (TM > 0) {
@@ -1058,6 +1119,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                     if (!iteration(t, ua[t < TM ? t : TM - 1], ua[t > 0 ? t - 1 : 0], st == NS - 1)) break;
                 k0 = g * P;                         // next step: same lanes, same slots,
                 sk = lane_on ? g : 0;               // columns one node further left
+                so = sk * SP;
+                sn = sk * SN;
                 --as;
             }
         }

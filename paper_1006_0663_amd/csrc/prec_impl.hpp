@@ -98,20 +98,23 @@ hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
                                                                r_out, d_out);
     coef_theta_kernel<T><<<(nth + 63) / 64, 64, 0, stream>>>(S.TP, S.dth, cos_out, sin2_out, J.wt);
     bool rows = false;
+    hipError_t ecopy = hipSuccess;
     if constexpr (W == 1) rows = J.onfly != 0;
     if (rows) {
         const double sh = mp_lead(S.hdt), sih = mp_lead(mp_mul(S.hdt, S.ih));
         const double sf = mp_lead(S.dt), sif = mp_lead(mp_mul(S.dt, S.ih));
         Fp64RowParams FP{J.nr, J.nr - 1, J.s, J.m, S.PP.mass, S.PP.a, sh, sih, sf, sif};
         coef_fp64_rows_kernel<<<(n + 127) / 128, 128, 0, stream>>>(FP, r_out, d_out, J.rf, J.rh);
-        hipMemcpyAsync(J.trig, cos_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
-        hipMemcpyAsync(J.trig + nth, sin2_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
+        ecopy = hipMemcpyAsync(J.trig, cos_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
+        if (ecopy == hipSuccess)
+            ecopy = hipMemcpyAsync(J.trig + nth, sin2_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
     } else {
         dim3 grid((nth + 63) / 64, n);
         coef_point_kernel<T><<<grid, 64, 0, stream>>>(S.PP, r_out, d_out, cos_out, sin2_out, S.hdt,
                                                        mp_mul(S.hdt, S.ih), S.dt, mp_mul(S.dt, S.ih), J.ch, J.cf);
     }
     err = hipGetLastError();
+    if (err == hipSuccess) err = ecopy;
     hipError_t e2 = hipStreamSynchronize(stream);
     if (err == hipSuccess) err = e2;
     e2 = hipFree(scratch);
