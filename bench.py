@@ -22,19 +22,46 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
-# HBM bytes per launch of the headline kernel, from rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE runs of paper_1006_0663_amd/profile_step.py (the summary under
-# profiles/ gives the commands).  FETCH_SIZE reads 131,093 KiB for a 256 MiB
-# device copy (scale 2.0), WRITE_SIZE 262,144 KiB (scale 1.0).  Valid only for
-# the launch shapes and kernel sources they were taken with: `source` is
-# kernel_source_digest() at that time; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {
-    "source": "e61ecaaf2706", "fetch_scale": 2.0, "write_scale": 1.0,
-    # (sweep, segcols, block, steps per launch): (FETCH_SIZE, WRITE_SIZE) KiB per launch
-    "per_shape": {(2, 4, 128, 1): (9429.2, 16384.0), (1, 4, 256, 1): (9380.7, 16384.0),
-                  (1, 8, 512, 1): (9373.7, 16384.0), (1, 6, 512, 1): (9363.2, 16384.0),
-                  (1, 8, 512, 2): (9471.7, 16384.0)},
+# Counter-derived figures, valid only for the launch shapes and kernel sources
+# they were taken with (`source` is kernel_source_digest() at that time;
+# otherwise they are reported as null); the summaries under profiles/ give the
+# commands (rocprofv3 --pmc on paper_1006_0663_amd/profile_step.py).
+#  traffic: HBM bytes per launch of the headline kernel, FETCH_SIZE and
+#    WRITE_SIZE in KiB; FETCH_SIZE reads 131,093 KiB for a 256 MiB device copy
+#    (scale 2.0), WRITE_SIZE 262,144 KiB (scale 1.0).  Key: (sweep, segcols,
+#    block, steps per launch).
+#  fp64_flops_hw: FP64 operations per update as the hardware counts them
+#    (SQ_INSTS_VALU_FLOPS_FP64 = 2 FMA + ADD + MUL wave instructions, x 64
+#    lanes, per launch, over the updates of that launch): unlike the operation
+#    tally of opcount.py this includes the halo columns each segment
+#    recomputes and lanes whose results are discarded.  Key: (workload,
+#    sweep, segcols, block, steps per launch).
+MEASURED = {
+    "source": "11e2e15d9e62", "fetch_scale": 2.0, "write_scale": 1.0,
+    "traffic": {(1, 8, 512, 2): (9469.2, 16384.0), (1, 4, 256, 1): (9378.6, 16384.0),
+                (2, 4, 128, 1): (9424.3, 16384.0), (1, 8, 512, 1): (9374.6, 16384.0),
+                (1, 6, 512, 1): (9355.2, 16384.0)},
+    "fp64_flops_hw": {
+        ("fp64-4096x128", 1, 8, 512, 2): 362.5, ("fp64-4096x128", 1, 4, 256, 1): 341.0,
+        ("fp64-4096x128", 2, 4, 128, 1): 341.0, ("fp64-4096x128", 1, 8, 512, 1): 341.0,
+        ("fp64-4096x128", 1, 6, 512, 1): 312.7,
+        ("dd-256x32", 1, 2, 256, 2): 5066.0, ("dd-256x32", 1, 2, 512, 2): 7802.0,
+        ("dd-256x32", 1, 4, 512, 2): 4359.7, ("dd-256x32", 1, 2, 0, 1): 2766.0,
+        ("dd-1024x64", 1, 4, 512, 2): 2880.7, ("dd-1024x64", 1, 4, 512, 1): 2414.7,
+        ("dd-1024x64", 1, 2, 256, 1): 2531.2,
+        ("qd-2048x64", 1, 4, 128, 1): 17077.4, ("qd-2048x64", 1, 8, 256, 1): 16593.9,
+        ("qd-2048x64", 1, 4, 256, 1): 19871.4,
+        ("dd-4096x128", 1, 8, 256, 1): 1844.8, ("dd-4096x128", 1, 16, 512, 1): 1815.7,
+        ("dd-4096x128", 1, 4, 256, 1): 2074.0,
+        ("qd-4096x128", 1, 8, 256, 1): 15200.7, ("qd-4096x128", 1, 4, 256, 1): 17081.2,
+    },
 }
+
+
+def measured(table, key):
+    if kernel_source_digest() != MEASURED["source"]:
+        return None
+    return MEASURED[table].get(tuple(key))
 
 
 def kernel_source_digest():
@@ -160,11 +187,11 @@ def main():
     achieved = bpu * pts * ns / launch_s / 1e9
     fpu = opcount.flops_per_update(1)
     traffic = traffic_bytes = None
-    m = MEASURED_TRAFFIC
-    kib = m["per_shape"].get(tuple(shape)) if kernel_source_digest() == m["source"] else None
+    kib = measured("traffic", shape)
     if kib:
-        traffic_bytes = 1024.0 * (kib[0] * m["fetch_scale"] + kib[1] * m["write_scale"])
+        traffic_bytes = 1024.0 * (kib[0] * MEASURED["fetch_scale"] + kib[1] * MEASURED["write_scale"])
         traffic = traffic_bytes / launch_s / 1e9
+    fhw = measured("fp64_flops_hw", (w.name,) + tuple(shape))
     out = {
         "metric": "grid-point updates/sec per precision (FP64/dd/qd) + % FP64 peak; batched vs plain",
         "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
@@ -185,24 +212,31 @@ def main():
                      "steps_per_launch": ns, "launch_us": launch_s * 1e6},
         "fp64_flops_per_update": fpu,
         "pct_fp64_peak": 100.0 * fpu * value / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
+        "fp64_flops_per_update_hw": fhw,
+        "pct_fp64_peak_hw": None if fhw is None else 100.0 * fhw * value / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
         "finite": finite,
         "wall_s_timed": wall,
     }
     if not args.headline_only:
         per = {"fp64-4096x128": {"words": 1, "steps": args.steps, "updates_per_s": value,
-                                 "pct_fp64_peak": out["pct_fp64_peak"]}}
-        for wx in (inputs.C3, inputs.C3_PARITY, inputs.C4):
+                                 "pct_fp64_peak": out["pct_fp64_peak"],
+                                 "pct_fp64_peak_hw": out["pct_fp64_peak_hw"]}}
+        for wx in (inputs.C3, inputs.C3_PARITY, inputs.C4, inputs.C2_DD, inputs.C2_QD):
             log("bench: timing %s (%d steps)" % (wx.name, wx.steps))
             fx = inputs.initial_fields(wx)
             msx, _, fin, shp = time_single(T, wx, fx, wx.steps, min(args.warmup, wx.steps // 10), args.graph,
                                            args.tile, torch, stream, log)
             ups = wx.n_r * wx.n_theta * wx.steps / (msx / 1e3)
             f = opcount.flops_per_update(wx.words)
+            fh = measured("fp64_flops_hw", (wx.name,) + tuple(shp))
             per[wx.name] = {"words": wx.words, "steps": wx.steps, "updates_per_s": ups,
                             "ms_per_step": msx / wx.steps, "sweep": ["segment", "wide", "wide2"][shp[0]],
                             "segcols": shp[1], "block": shp[2], "steps_per_launch": shp[3],
                             "fp64_flops_per_update": f,
                             "pct_fp64_peak": 100.0 * f * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
+                            "fp64_flops_per_update_hw": fh,
+                            "pct_fp64_peak_hw": None if fh is None else
+                            100.0 * fh * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
                             "hbm_GBs_algorithmic": opcount.bytes_per_update(wx.words) * ups / 1e9,
                             "finite": fin}
         out["per_precision"] = per

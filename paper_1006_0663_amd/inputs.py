@@ -71,7 +71,12 @@ C3 = Workload("dd-256x32", s=-2, m=2, a_over_M=0.5, n_r=256, n_theta=32, rstar_m
 C3_PARITY = C3.with_(name="dd-1024x64", n_r=1024, n_theta=64)
 C4 = Workload("qd-2048x64", s=-2, m=2, a_over_M=0.99, n_r=2048, n_theta=64, rstar_min=-200.0,
               rstar_max=800.0, words=4, steps=5000, amplitude="normal", cfl=LONG_RUN_CFL)
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C3_PARITY, C4)}
+# The headline grid in double-double and quad-double: single instances large
+# enough to fill the GPU, for the sustained multiword throughput (the dd and
+# qd workloads above are parity sizes).
+C2_DD = C2.with_(name="dd-4096x128", words=2, steps=2000)
+C2_QD = C2.with_(name="qd-4096x128", words=4, steps=500)
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C3_PARITY, C4, C2_DD, C2_QD)}
 
 BATCH_RSTAR = (-200.0, 800.0)
 BATCH_NR = (1024, 2048, 4096, 8192)
