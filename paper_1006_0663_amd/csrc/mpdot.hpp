@@ -6,14 +6,20 @@
 // double: a chain of FMAs.
 // double-double: the products' leading parts are summed exactly (two_prod
 //   and two_sum, errors pushed to the next order); all order-u terms (product
-//   errors, cross products, low words, two_sum errors) go into one double with
-//   FMAs.  Absolute error O(u^2) sum_k |a_k b_k| + O(u^2) sum_l |v_l|, the same
-//   order as a sequence of double-double operations (Ogita-Rump-Oishi
-//   compensated dot product, extended to double-double inputs).
+//   errors, cross products, low words, two_sum errors) go into one double.
+//   Absolute error O(u^2) sum_k |a_k b_k| + O(u^2) sum_l |v_l|, the same order
+//   as a sequence of double-double operations (Ogita-Rump-Oishi compensated
+//   dot product, extended to double-double inputs).
 // quad-double: four running sums s0..s3, one per order u^0..u^3; the terms of
 //   orders 0, 1 and 2 are added with two_sum and their errors passed one order
 //   down, the order-3 terms with plain additions; the product terms of order
 //   4 and below are dropped.  Absolute error O(u^4) (sum |a_k b_k| + sum |v_l|).
+// In quad-double a product's own lower-order terms are first combined among
+// themselves (exactly where the order requires it), off the running sums'
+// dependency chains: each running sum then sees two to four additions per
+// product instead of up to ten, so consecutive products overlap in the
+// pipeline (measured: 4 % faster on the 2048 x 64 grid; the same treatment of
+// the double-double sum gained nothing).
 //
 // Operands are non-overlapping expansions; results are renormalised.
 #pragma once
@@ -68,20 +74,28 @@ template <> struct Acc<qd> {
         two_prod(a.x0, b.x2, p02, q02);
         two_prod(a.x1, b.x1, p11, q11);
         two_prod(a.x2, b.x0, p20, q20);
-        two_sum(s0, p00, s0, t);
-        o1(t);
-        o1(q00);
-        o1(p01);
-        o1(p10);
-        o2(q01);
-        o2(q10);
-        o2(p02);
-        o2(p11);
-        o2(p20);
+        // order 1 of the product: p01 + p10 + q00 = u1 + (e1 + e2 at order 2)
+        double u1, e1, e2;
+        two_sum(p01, p10, u1, e1);
+        two_sum(u1, q00, u1, e2);
+        // order 2: p02 + p11 + p20 + q01 + q10 + e1 + e2 = u2 + (f1..f6 at order 3)
+        double u2, v2, v3, f1, f2, f3, f4, f5, f6;
+        two_sum(p02, p11, u2, f1);
+        two_sum(p20, q01, v2, f2);
+        two_sum(q10, e1, v3, f3);
+        two_sum(u2, v2, u2, f4);
+        two_sum(v3, e2, v3, f5);
+        two_sum(u2, v3, u2, f6);
+        // order 3, rounded
         double o3 = fma(a.x0, b.x3, a.x1 * b.x2);
         o3 = fma(a.x2, b.x1, o3);
         o3 = fma(a.x3, b.x0, o3);
-        s3 += ((q02 + q11) + q20) + o3;
+        const double u3 = (((q02 + q11) + q20) + o3) + (((f1 + f2) + (f3 + f4)) + (f5 + f6));
+        two_sum(s0, p00, s0, t);
+        o1(t);
+        o1(u1);
+        o2(u2);
+        s3 += u3;
     }
     MPA void value(const qd &v) {
         double t;
