@@ -598,18 +598,12 @@ __device__ __forceinline__ cx<T> theta_stencil(const d2 *base, int stride, int j
     return {re.result(), im.result()};
 }
 
-// eight coefficients of node/half node i at row j: from the stored planes, or
-// (FP64 per-point mode, ONFLY) rebuilt from the radial row staged in LDS
-template <class T, bool ONFLY>
-__device__ __forceinline__ void load_coef(const GLB double *planes, const double *lrow, uint32_t plane, uint32_t idx,
-                                          double cs, double s2, T *c) {
+// eight coefficients of node/half node idx at its row, from the stored planes
+template <class T>
+__device__ __forceinline__ void load_coef(const GLB double *planes, uint32_t plane, uint32_t idx, T *c) {
     constexpr uint32_t W = words_of<T>::value;
-    if constexpr (W == 1 && ONFLY) {
-        coef_fp64_point(lrow, cs, s2, c);
-    } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = gld<T>(planes + q * W * plane, plane, idx);
-    }
+    for (int q = 0; q < 8; ++q) c[q] = gld<T>(planes + q * W * plane, plane, idx);
 }
 
 // one stage at node/half node idx: coefficients from the stored planes, or
@@ -622,7 +616,7 @@ __device__ __forceinline__ Pt<T> stage_at(const GLB double *planes, const double
         return lw_stage_row(base, bar, d, lbar, lrow, cs, s2, s);
     } else {
         T c[8];
-        load_coef<T, false>(planes, lrow, plane, idx, cs, s2, c);
+        load_coef<T>(planes, plane, idx, c);
         return lw_stage(base, bar, d, lbar, c, s);
     }
 }
@@ -722,8 +716,7 @@ __global__ __launch_bounds__(NT) LWK_STEP_OCC void lw_step_kernel(const InstDev 
             // (lw1) at half node col-1/2 (index col-1)
             const bool h_on = seg_on && col <= e && t >= 1;
             T cf[8];
-            load_coef<T, false>(gptr(I.ch), nullptr, hplane, (uint32_t)(min(max(col - 1, 0), nr - 2) * nth + j), 0.0,
-                                0.0, cf);
+            load_coef<T>(gptr(I.ch), hplane, (uint32_t)(min(max(col - 1, 0), nr - 2) * nth + j), cf);
             const Pt<T> bar = pt_avg(u_prev, u_cur);
             const Pt<T> uh_cur = lw_stage(bar, bar, pt_diff(u_prev, u_cur), c_avg(l_prev, l_cur), cf, hdt);
             if (lane_on) xput<T>(xh, NT, slot, uh_cur.phi);
@@ -732,7 +725,7 @@ __global__ __launch_bounds__(NT) LWK_STEP_OCC void lw_step_kernel(const InstDev 
             if (h_on && t >= 2) {
                 // (lw2) at node col-1
                 const int i = col - 1;
-                load_coef<T, false>(gptr(I.cf), nullptr, plane, (uint32_t)(i * nth + j), 0.0, 0.0, cf);
+                load_coef<T>(gptr(I.cf), plane, (uint32_t)(i * nth + j), cf);
                 const Pt<T> un = lw_stage(u_prev, pt_avg(uh_prev, uh_cur), pt_diff(uh_prev, uh_cur),
                                           c_avg(lh_prev, lh_cur), cf, dt);
                 gst_pt(uout, plane, (uint32_t)(i * nth + j), un);

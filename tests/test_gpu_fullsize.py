@@ -29,15 +29,29 @@ def load(path):
     return w, z["points"], z["values"], _value(z["maxabs"])
 
 
+@pytest.mark.parametrize("mode", ["default", "tuned"])
 @pytest.mark.parametrize("path", FILES, ids=[os.path.basename(f)[:-4] for f in FILES])
-def test_full_size_parity(path):
+def test_full_size_parity(path, mode, tmp_path, monkeypatch):
+    """mode "default": the library's launch shape; "tuned": the shape the
+    autotuner picks with graphs on, which is how bench.py times a workload
+    (fused multi-step launches included)."""
     w, pts, vals, maxabs = load(path)
-    print("full-size parity %s: %dx%d words=%d steps=%d cfl=%g" % (w.name, w.n_r, w.n_theta, w.words, w.steps,
-                                                                    w.cfl), flush=True)
+    print("full-size parity %s (%s launch shape): %dx%d words=%d steps=%d cfl=%g"
+          % (w.name, mode, w.n_r, w.n_theta, w.words, w.steps, w.cfl), flush=True)
     g = T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
     h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
     h.use_graph(100)                       # as bench.py times it
     h.set_initial(*inputs.initial_fields(w))
+    if mode == "tuned":
+        import torch
+        from paper_1006_0663_amd import autotune
+        monkeypatch.setenv("TEUK_TUNE_CACHE", str(tmp_path / "cache.json"))
+        torch.cuda.set_device(0)
+        stream = torch.cuda.Stream()
+        h.set_stream(stream.cuda_stream)
+        shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream, steps=200)
+        print("  tuned shape (sweep, segcols, block, steps per launch, us): %s" % (shape,), flush=True)
+        h.set_initial(*inputs.initial_fields(w))
     h.step(w.steps)
     got = [h.read_field(c).reshape(-1, w.words) for c in range(4)]
     h.close()
