@@ -121,7 +121,10 @@ int teuk_words(const teuk_t *h);
 /* Restore the step counter after a checkpoint restart (fields via set_initial). */
 int teuk_set_step_index(teuk_t *h, long n);
 
-/* Run subsequent work on the given hipStream_t (0 = the library's own stream). */
+/* Run subsequent work on the given hipStream_t (0 = the library's own stream).
+ * Waits for the work queued on the current stream first; a device error found
+ * then returns TEUK_EDEVICE and leaves the handle failed (as do teuk_set_launch,
+ * teuk_set_sweep, teuk_set_fuse and teuk_set_tile, which wait the same way). */
 int teuk_set_stream(teuk_t *h, void *hip_stream);
 
 /* Set *ok to 1 if every field word is finite, else 0 (returns TEUK_ENONFINITE then). */

@@ -465,6 +465,19 @@ int check_ok(Batch &b) {
     return TEUK_OK;
 }
 
+// Wait for the handle's queued work (before its launch shape or stream
+// changes); a device error found here puts the handle in the failed state.
+int quiesce(Batch &b) {
+    if (int rc = check_ok(b)) return rc;
+    if (!b.stream) return TEUK_OK;
+    const hipError_t e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "stream synchronize");
+    }
+    return TEUK_OK;
+}
+
 // host interchange [j][i][w]  <->  device planar [w][i][j]
 int upload_field(Batch &b, Instance &I, int comp, const double *src, int buf) {
     const int W = I.words, nr = I.g.n_r, nth = I.g.n_theta;
@@ -588,7 +601,7 @@ int read_field(Batch &b, int k, int f, double *out) {
 }
 
 int set_stream(Batch &b, void *st) {
-    if (b.stream) hipStreamSynchronize(b.stream);
+    if (int rc = quiesce(b)) return rc;
     b.stream = st ? (hipStream_t)st : b.own_stream;
     drop_graph(b);
     return TEUK_OK;
@@ -669,8 +682,7 @@ int teuk_use_graph(teuk_t *h, int k) {
 }
 int teuk_set_tile(teuk_t *h, int segcols) {
     if (!h || segcols < 1) return fail(TEUK_EINVAL, "bad handle or tile");
-    if (int rc = check_ok(h->b)) return rc;
-    hipStreamSynchronize(h->b.stream);
+    if (int rc = quiesce(h->b)) return rc;
     h->b.segcols = segcols;
     return build_worklist(h->b);
 }
@@ -681,8 +693,7 @@ static int set_launch(Batch &b, int segcols, int block) {
     int maxnth = 0;
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     if (block != 0 && block < maxnth) return fail(TEUK_EINVAL, "block must be >= n_theta");
-    if (int rc = check_ok(b)) return rc;
-    hipStreamSynchronize(b.stream);
+    if (int rc = quiesce(b)) return rc;
     const int old_seg = b.segcols, old_nt = b.nt_req;
     b.segcols = segcols;
     b.nt_req = block;
@@ -703,8 +714,7 @@ static int set_sweep(Batch &b, int sweep) {
         return fail(TEUK_EINVAL, "sweep must be -1 (default), 0 (segment), 1 (wide) or 2 (wide, runs of two)");
     if (sweep == TEUK_SWEEP_WIDE2 && b.words != 1)
         return fail(TEUK_ENOTSUP, "the wide sweep with runs of two columns is built for FP64 only");
-    if (int rc = check_ok(b)) return rc;
-    hipStreamSynchronize(b.stream);
+    if (int rc = quiesce(b)) return rc;
     const int old = b.sweep_req, old_nt = b.nt_req;
     b.sweep_req = sweep;
     b.nt_req = 0;
@@ -731,8 +741,7 @@ int teuk_get_sweep(const teuk_t *h) { return h ? h->b.sweep : TEUK_EINVAL; }
 
 static int set_fuse(Batch &b, int ns) {
     if (ns != 1 && ns != 2 && ns != 4) return fail(TEUK_EINVAL, "steps per launch must be 1, 2 or 4");
-    if (int rc = check_ok(b)) return rc;
-    hipStreamSynchronize(b.stream);
+    if (int rc = quiesce(b)) return rc;
     const int old = b.fuse;
     b.fuse = ns;
     int rc = build_worklist(b);
@@ -811,8 +820,10 @@ int teuk_get_coefficients(teuk_t *h, int which, double *out) {
     for (int c = 0; c < 8 && rc == TEUK_OK; ++c)
         rc = download_planes(b, src + (size_t)c * W * plane, 1, nr, nth, W, out + (size_t)c * plane * W);
     if (tmp) {
-        hipStreamSynchronize(b.stream);
-        hipFree(tmp);
+        const hipError_t e = hipStreamSynchronize(b.stream);
+        const hipError_t e2 = hipFree(tmp);
+        if (rc == TEUK_OK && e != hipSuccess) rc = hip_fail(e, "stream synchronize");
+        if (rc == TEUK_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipFree");
     }
     return rc;
 }
@@ -895,8 +906,7 @@ double teuk_batch_dt(const teuk_batch_t *b, int k) {
 }
 int teuk_batch_set_tile(teuk_batch_t *b, int segcols) {
     if (!b || segcols < 1) return fail(TEUK_EINVAL, "bad handle or tile");
-    if (int rc = check_ok(b->b)) return rc;
-    hipStreamSynchronize(b->b.stream);
+    if (int rc = quiesce(b->b)) return rc;
     b->b.segcols = segcols;
     return build_worklist(b->b);
 }
