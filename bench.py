@@ -117,7 +117,7 @@ def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=Non
     return ms, wall, finite, shape
 
 
-def cpu_baseline(w, seconds_target=22.0):
+def cpu_baseline(w, seconds_target=22.0, single_core_seconds=6.0):
     """The oracle (C fixed-point engine, all host cores) on a radial slab of the
     headline workload: 512 r* nodes around the pulse x all theta rows."""
     from paper_1006_0663_amd import inputs
@@ -143,10 +143,32 @@ def cpu_baseline(w, seconds_target=22.0):
     t0 = time.perf_counter()
     engine.run_fixed(FT, nslab, w.n_theta, u, nsteps, threads=cores)
     dt = time.perf_counter() - t0
+    # one core, as the paper's CPU baseline ran: a shorter sample of the same slab
+    t0 = time.perf_counter()
+    engine.run_fixed(FT, nslab, w.n_theta, u, 1, threads=1)
+    one1 = time.perf_counter() - t0
+    n1 = max(1, int(single_core_seconds / max(one1, 1e-3)))
+    t0 = time.perf_counter()
+    engine.run_fixed(FT, nslab, w.n_theta, u, n1, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": nslab * w.n_theta * nsteps / dt, "unit": "grid-point updates/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d steps of a %d x %d r*-slab (nodes %d..%d) of the headline grid, 384-bit fixed point, %.1f s"
-                      % (nsteps, nslab, w.n_theta, i0, i0 + nslab - 1, dt)}
+                      % (nsteps, nslab, w.n_theta, i0, i0 + nslab - 1, dt),
+            "cpu_model": _cpu_model(),
+            "single_core": {"value": nslab * w.n_theta * n1 / dt1, "unit": "grid-point updates/s", "cores": 1,
+                            "sample": "%d steps of the same slab on one thread, %.1f s" % (n1, dt1)}}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
