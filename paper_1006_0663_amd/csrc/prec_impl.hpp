@@ -194,8 +194,9 @@ hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev 
     constexpr int W = words_of<T>::value;
     constexpr bool has_one = W == 1;
     // fused forms: runs of one column, one or two unrolled iterations (FP64:
-    // up to four for two steps per launch)
-    constexpr bool fused = TM >= 1 && TM <= (W == 1 ? 4 : 2) && P == 1 && (W == 2 || (W == 1 && CM > 0));
+    // up to four for two steps per launch, or runs of two with up to three)
+    constexpr bool fused = TM >= 1 && TM <= (W == 1 ? 4 : 2) && (P == 1 || (W == 1 && TM <= 3)) &&
+                           (W == 2 || (W == 1 && CM > 0));
     const bool o = has_one && one;
     if (ns == 1) {
         if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 1>(lds, one, insts, items, nitems, parity, stream, attr_only);
@@ -206,7 +207,7 @@ hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev 
             if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
             return wide_launch_one<T, NT, P, CM, TM, false, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
         }
-        if (ns == 4 && TM <= 2) {
+        if (ns == 4 && TM <= 2 && P == 1) {
             if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
             return wide_launch_one<T, NT, P, CM, TM, false, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
         }

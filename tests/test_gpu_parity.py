@@ -217,6 +217,32 @@ def test_fused_steps_are_bitwise(words, nth, block, seg, fuse):
     assert rel_linf(ref, oracle_run(w, fields, 11)) <= TOL[words]
 
 
+# FP64 runs of two columns, two steps per launch: (n_theta, block, segcols)
+FUSED_RUN2 = [(64, 256, 8), (128, 256, 8), (128, 256, 6), (64, 512, 12), (64, 256, 11)]
+
+
+@pytest.mark.parametrize("nth,block,seg", FUSED_RUN2, ids=["t%d-b%d-s%d" % c for c in FUSED_RUN2])
+def test_fused_runs_of_two_are_bitwise(nth, block, seg):
+    """Two steps per launch with runs of two columns per lane give the bits of
+    single steps (default launch), with and without graph replay."""
+    w = inputs.C1.with_(n_r=47, n_theta=nth, rstar_min=60.0, rstar_max=150.0, m=1, a_over_M=0.8)
+    fields = inputs.initial_fields(w)
+    _note("fused runs of two: n_theta=%d block=%d segcols=%d" % (nth, block, seg))
+    ref = _run_gpu(w, fields, 11)
+    for graph in (0, 4):
+        h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 1)
+        h.set_sweep(T.SWEEP_WIDE2)
+        h.set_launch(seg, block)
+        h.set_fuse(2)
+        h.use_graph(graph)
+        h.set_initial(*fields)
+        h.step(11)
+        got = h.fields()
+        h.close()
+        for f in range(4):
+            assert np.array_equal(got[f], ref[f]), (graph, f)
+
+
 def test_fused_batch_equals_single():
     ws = [inputs.C1.with_(n_r=30 + 11 * k, n_theta=32, rstar_min=60.0, rstar_max=150.0, m=k, a_over_M=0.3 * k,
                           words=2, seed=k) for k in range(3)]
