@@ -25,7 +25,7 @@ CANDIDATES = {
     2: [(WIDE, s, b, 1) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12, 16)]
        + [(SEGMENT, 2, 0, 1), (SEGMENT, 2, 128, 1)]
        + [(WIDE, s, b, 2) for b in (256, 512) for s in (2, 4)],
-    4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)],
+    4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12, 16)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)],
 }
 
 
