@@ -155,12 +155,16 @@ int teuk_get_sweep(const teuk_t *h);
 
 /* Time steps per kernel launch (1, 2 or 4; results are bitwise the same).
  * With k > 1 each launch advances k steps of a segment from registers,
- * reading k extra columns on each side (so small grids, whose steps are bound
- * by launch and memory latency, take fewer of both).  Needs the wide sweep
- * with runs of one column, dd or FP64 with per-point coefficients, blocks of
- * 128..512 threads and segcols + 3k <= 2 * block / n_theta; otherwise
- * TEUK_EINVAL and the previous setting stays.  teuk_step(n) runs n / k fused
- * launches and the remainder one step per launch. */
+ * reading k extra columns on each side (so grids whose steps are bound by
+ * launch and memory latency take fewer of both).  Needs the wide sweep, dd or
+ * FP64 with per-point coefficients, blocks of 128..512 threads, and every
+ * work item's columns (segcols + 2k, plus k padding columns where a segment
+ * reaches the right boundary) within the unrolled iterations: at most 2 x
+ * block / n_theta with runs of one column, or for FP64 with k = 2 at most
+ * 4 x block / n_theta (runs of one) or 3 x 2 x block / n_theta (runs of two,
+ * TEUK_SWEEP_WIDE2); otherwise TEUK_EINVAL and the previous setting stays.
+ * teuk_step(n) runs n / k fused launches and the remainder one step per
+ * launch. */
 int teuk_set_fuse(teuk_t *h, int steps_per_launch);
 
 /* Test hooks: the eight scaled coefficients at half nodes (which = 0,
