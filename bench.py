@@ -61,6 +61,7 @@ MEASURED = {
         ("dd-4096x128", 1, 8, 256, 1): 1844.8, ("dd-4096x128", 1, 16, 512, 1): 1815.7,
         ("dd-4096x128", 1, 4, 256, 1): 2074.0,
         ("qd-4096x128", 1, 8, 256, 1): 15200.7, ("qd-4096x128", 1, 4, 256, 1): 17081.2,
+        ("qd-4096x128", 1, 16, 256, 1): 14260.5,
     },
 }
 
