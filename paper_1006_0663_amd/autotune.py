@@ -23,6 +23,7 @@ CANDIDATES = {
        + [(WIDE, s, b, f) for f in (2, 4) for b in (256, 512) for s in (2, 4)]
        + [(WIDE, s, 512, 2) for s in (6, 8)] + [(WIDE2, 8, 256, 2), (WIDE2, 16, 512, 2)],
     2: [(WIDE, s, b, 1) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12, 16)]
+       + [(WIDE, s, 512, 1) for s in (24, 32)]
        + [(SEGMENT, 2, 0, 1), (SEGMENT, 2, 128, 1)]
        + [(WIDE, s, b, 2) for b in (256, 512) for s in (2, 4)],
     4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12, 16)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)],
