@@ -1,6 +1,6 @@
 """Grid, time step and coefficient tables of one Teukolsky problem (test infrastructure).
 
-Readings of the paper (it fixes none of these; each is listed in the design doc):
+Readings of the paper (it fixes none of these):
 
 * r* grid: n_r vertex-centred nodes r*_i = r*_min + i h, h = (r*_max - r*_min)/(n_r - 1),
   i = 0..n_r-1; the first and last node carry the Dirichlet condition

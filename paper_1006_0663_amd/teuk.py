@@ -85,7 +85,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libteuk.so is not built (run __graft_entry__.build()); "
+            raise RuntimeError("libteuk.so is not built (python -m paper_1006_0663_amd.build); "
                                "there is no fallback implementation")
         # PyTorch ships its own HIP runtime under a different file name; loaded
         # first, it also serves this library (same soname), so the process holds
