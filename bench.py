@@ -147,6 +147,7 @@ def cpu_baseline(w, seconds_target=22.0, single_core_seconds=6.0):
     t0 = time.perf_counter()
     engine.run_fixed(FT, nslab, w.n_theta, u, nsteps, threads=cores)
     dt = time.perf_counter() - t0
+    cores = engine.threads_in_use()
     # one core, as the paper's CPU baseline ran: a shorter sample of the same slab
     t0 = time.perf_counter()
     engine.run_fixed(FT, nslab, w.n_theta, u, 1, threads=1)
@@ -161,7 +162,8 @@ def cpu_baseline(w, seconds_target=22.0, single_core_seconds=6.0):
                       % (nsteps, nslab, w.n_theta, i0, i0 + nslab - 1, dt),
             "cpu_model": _cpu_model(),
             "single_core": {"value": nslab * w.n_theta * n1 / dt1, "unit": "grid-point updates/s", "cores": 1,
-                            "sample": "%d steps of the same slab on one thread, %.1f s" % (n1, dt1)}}
+                            "sample": "%d steps of the same slab on one thread, %.1f s" % (n1, dt1),
+                            "threads_checked": engine.threads_in_use()}}
 
 
 def _cpu_model():

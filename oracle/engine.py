@@ -41,6 +41,8 @@ def _load():
         lib.oracle_lw_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_int,
                                       ctypes.c_int, p, p, p, p, p, p, p, p]
         lib.oracle_lw_run.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         assert lib.oracle_fx_limbs() == NL and lib.oracle_fx_frac_bits() == FRAC
         _lib = lib
     return _lib
@@ -151,7 +153,7 @@ def run_fixed(FT, nr: int, nth: int, u_ints: list, nsteps: int, threads: int = 0
     """Advance fixed-point state (flat ints [4][nth][nr]) by nsteps; returns ints."""
     lib = _load()
     if threads:
-        os.environ["OMP_NUM_THREADS"] = str(threads)
+        lib.oracle_set_threads(int(threads))
     u = ints_to_limbs(u_ints)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     rc = lib.oracle_lw_run(nr, nth, nsteps, FT["reach"], FT["parity"], ptr(FT["half"]),
@@ -160,6 +162,11 @@ def run_fixed(FT, nr: int, nth: int, u_ints: list, nsteps: int, threads: int = 0
     if rc != 0:
         raise ArithmeticError("oracle engine failed with code %d" % rc)
     return limbs_to_ints(u)
+
+
+def threads_in_use() -> int:
+    """Threads the engine's parallel loops run on now."""
+    return _load().oracle_set_threads(0)
 
 
 def fixed_to_float(vals) -> np.ndarray:

@@ -26,6 +26,7 @@
  *   d1, d2    [2R+1]              stencil weights already divided by dtheta, dtheta^2
  *   scal      [2]                 inv_h = 1/dr*, dt
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -226,6 +227,13 @@ static void lw_step(const ctx_t *c, const cx *phi, const cx *pi, cx *phih, cx *p
     memset(&npi[0], 0, sizeof(cx) * nth);
     memset(&nphi[(size_t)(nr - 1) * nth], 0, sizeof(cx) * nth);
     memset(&npi[(size_t)(nr - 1) * nth], 0, sizeof(cx) * nth);
+}
+
+/* Threads of the parallel loops (n > 0; the OpenMP runtime reads
+ * OMP_NUM_THREADS only once); returns the count now in effect. */
+int oracle_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 int oracle_fx_limbs(void) { return NL; }
