@@ -43,11 +43,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # changes since were host-side or did not alter the generated kernels.)
 MEASURED = {
     "source": "a95add959460", "fetch_scale": 2.0, "write_scale": 1.0,
-    "traffic": {(2, 8, 256, 2): (9592.8, 16384.0), (2, 16, 512, 2): (9598.8, 16384.0),
+    "traffic": {(2, 16, 512, 4): (9886.8, 16384.0),
+                (2, 8, 256, 2): (9592.8, 16384.0), (2, 16, 512, 2): (9598.8, 16384.0),
                 (1, 8, 512, 2): (9469.2, 16384.0), (1, 4, 256, 1): (9378.6, 16384.0),
                 (2, 4, 128, 1): (9424.3, 16384.0), (1, 8, 512, 1): (9374.6, 16384.0),
                 (1, 6, 512, 1): (9355.2, 16384.0)},
     "fp64_flops_hw": {
+        ("fp64-4096x128", 2, 16, 512, 4): 373.2,
         ("fp64-4096x128", 2, 8, 256, 2): 362.5, ("fp64-4096x128", 2, 16, 512, 2): 362.5,
         ("fp64-4096x128", 1, 8, 512, 2): 362.5, ("fp64-4096x128", 1, 4, 256, 1): 341.0,
         ("fp64-4096x128", 2, 4, 128, 1): 341.0, ("fp64-4096x128", 1, 8, 512, 1): 341.0,

@@ -159,9 +159,9 @@ int teuk_get_sweep(const teuk_t *h);
  * launch and memory latency take fewer of both).  Needs the wide sweep, dd or
  * FP64 with per-point coefficients, blocks of 128..512 threads, and every
  * work item's columns (segcols + 2k, plus k padding columns where a segment
- * reaches the right boundary) within the unrolled iterations: at most 2 x
- * block / n_theta with runs of one column, or for FP64 with k = 2 at most
- * 4 x block / n_theta (runs of one) or 3 x 2 x block / n_theta (runs of two,
+ * reaches the right boundary) within the unrolled iterations: for dd at most
+ * 2 x block / n_theta (runs of one column), for FP64 at most 4 x block /
+ * n_theta (runs of one) or 3 x 2 x block / n_theta (runs of two,
  * TEUK_SWEEP_WIDE2); otherwise TEUK_EINVAL and the previous setting stays.
  * teuk_step(n) runs n / k fused launches and the remainder one step per
  * launch. */

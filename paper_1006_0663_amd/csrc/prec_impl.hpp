@@ -193,10 +193,10 @@ hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev 
                          int nitems, int parity, hipStream_t stream, bool attr_only) {
     constexpr int W = words_of<T>::value;
     constexpr bool has_one = W == 1;
-    // fused forms: runs of one column, one or two unrolled iterations (FP64:
-    // up to four for two steps per launch, or runs of two with up to three)
-    constexpr bool fused = TM >= 1 && TM <= (W == 1 ? 4 : 2) && (P == 1 || (W == 1 && TM <= 3)) &&
-                           (W == 2 || (W == 1 && CM > 0));
+    // fused forms (2 or 4 steps per launch): dd with runs of one column and one
+    // or two unrolled iterations; FP64 (per-point coefficients) with runs of
+    // one column and up to four iterations, or runs of two and up to three
+    constexpr bool fused = TM >= 1 && (W == 1 ? CM > 0 && (P == 1 ? TM <= 4 : TM <= 3) : W == 2 && P == 1 && TM <= 2);
     const bool o = has_one && one;
     if (ns == 1) {
         if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 1>(lds, one, insts, items, nitems, parity, stream, attr_only);
@@ -207,7 +207,7 @@ hipError_t wide_launch_k(int ns, size_t lds, const WideArgs *one, const InstDev 
             if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
             return wide_launch_one<T, NT, P, CM, TM, false, 2>(lds, one, insts, items, nitems, parity, stream, attr_only);
         }
-        if (ns == 4 && TM <= 2 && P == 1) {
+        if (ns == 4) {
             if (o) return wide_launch_one<T, NT, P, CM, TM, has_one, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
             return wide_launch_one<T, NT, P, CM, TM, false, 4>(lds, one, insts, items, nitems, parity, stream, attr_only);
         }

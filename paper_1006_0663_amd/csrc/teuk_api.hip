@@ -292,16 +292,16 @@ int build_worklist(Batch &b) {
         }
         b.tm = ti <= 4 ? ti : 0;
         if (b.fuse > 1) {
-            const int max_tm = b.words == 1 && b.fuse == 2 ? 4 : 2;
-            const bool runs_ok = wide_run(b.sweep) == 1 || (b.words == 1 && b.fuse == 2 && b.tm <= 3);
-            const bool ok = b.tm >= 1 && b.tm <= max_tm && runs_ok && b.nt >= 128 && b.nt <= 512 &&
-                            (b.words == 2 || (b.words == 1 && b.cmode > 0));
+            const int run = wide_run(b.sweep);
+            const int max_tm = b.words == 1 ? (run == 1 ? 4 : 3) : 2;
+            const bool ok = b.tm >= 1 && b.tm <= max_tm && b.nt >= 128 && b.nt <= 512 &&
+                            ((b.words == 2 && run == 1) || (b.words == 1 && b.cmode > 0));
             if (!ok)
-                return fail(TEUK_EINVAL, "fused steps need dd or FP64 per-point coefficients, blocks of 128-512 "
-                                         "threads and runs of one column with at most two iterations per step "
-                                         "(FP64, two steps per launch: four; or FP64 runs of two columns, two "
-                                         "steps per launch, three), i.e. segcols + 2 * fuse columns (+ fuse past "
-                                         "the right boundary) within iterations * run * block / n_theta");
+                return fail(TEUK_EINVAL, "fused steps need blocks of 128-512 threads and either dd with runs of "
+                                         "one column and at most two iterations per step, or FP64 per-point "
+                                         "coefficients with at most four iterations (runs of one column) or "
+                                         "three (runs of two): segcols + 2 * fuse columns (+ fuse past the "
+                                         "right boundary) within iterations * run * block / n_theta");
         }
         if (b.lds > 64 * 1024) {
             const int run = wide_run(b.sweep);

@@ -217,23 +217,30 @@ def test_fused_steps_are_bitwise(words, nth, block, seg, fuse):
     assert rel_linf(ref, oracle_run(w, fields, 11)) <= TOL[words]
 
 
-# FP64 runs of two columns, two steps per launch: (n_theta, block, segcols)
-FUSED_RUN2 = [(64, 256, 8), (128, 256, 8), (128, 256, 6), (64, 512, 12), (64, 256, 11)]
+# FP64 fused launches beyond the forms above: (sweep, n_theta, block, segcols,
+# steps per launch) -- runs of two columns (up to three iterations) with two
+# or four steps, runs of one with four steps and three or four iterations;
+# the segment lengths leave ragged last segments, some shorter than the steps
+FUSED_FP64 = [(T.SWEEP_WIDE2, 64, 256, 8, 2), (T.SWEEP_WIDE2, 128, 256, 8, 2), (T.SWEEP_WIDE2, 128, 256, 6, 2),
+              (T.SWEEP_WIDE2, 64, 512, 12, 2), (T.SWEEP_WIDE2, 64, 256, 11, 2), (T.SWEEP_WIDE2, 64, 512, 16, 4),
+              (T.SWEEP_WIDE2, 128, 512, 16, 4), (T.SWEEP_WIDE2, 64, 512, 13, 4), (T.SWEEP_WIDE, 64, 256, 8, 4),
+              (T.SWEEP_WIDE, 128, 512, 8, 4), (T.SWEEP_WIDE, 64, 512, 23, 4)]
 
 
-@pytest.mark.parametrize("nth,block,seg", FUSED_RUN2, ids=["t%d-b%d-s%d" % c for c in FUSED_RUN2])
-def test_fused_runs_of_two_are_bitwise(nth, block, seg):
-    """Two steps per launch with runs of two columns per lane give the bits of
-    single steps (default launch), with and without graph replay."""
+@pytest.mark.parametrize("sweep,nth,block,seg,fuse", FUSED_FP64,
+                         ids=["r%d-t%d-b%d-s%d-f%d" % (c[0], c[1], c[2], c[3], c[4]) for c in FUSED_FP64])
+def test_fused_fp64_forms_are_bitwise(sweep, nth, block, seg, fuse):
+    """Several steps per launch give the bits of single steps (default
+    launch), with and without graph replay."""
     w = inputs.C1.with_(n_r=47, n_theta=nth, rstar_min=60.0, rstar_max=150.0, m=1, a_over_M=0.8)
     fields = inputs.initial_fields(w)
-    _note("fused runs of two: n_theta=%d block=%d segcols=%d" % (nth, block, seg))
+    _note("fused FP64: sweep=%d n_theta=%d block=%d segcols=%d fuse=%d" % (sweep, nth, block, seg, fuse))
     ref = _run_gpu(w, fields, 11)
     for graph in (0, 4):
         h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 1)
-        h.set_sweep(T.SWEEP_WIDE2)
+        h.set_sweep(sweep)
         h.set_launch(seg, block)
-        h.set_fuse(2)
+        h.set_fuse(fuse)
         h.use_graph(graph)
         h.set_initial(*fields)
         h.step(11)
