@@ -294,6 +294,27 @@ def test_autotuned_shape_is_bitwise(words, tmp_path, monkeypatch):
         assert np.array_equal(got[f], ref[f]), f
 
 
+def test_fused_fp64_batch_equals_single():
+    """An FP64 batch of uneven instances with four steps per launch and runs of
+    two columns gives each instance the bits of its own single-step run."""
+    ws = [inputs.C1.with_(n_r=30 + 13 * k, n_theta=(64, 128, 64)[k], rstar_min=60.0, rstar_max=150.0, m=k,
+                          a_over_M=0.3 * k, seed=k) for k in range(3)]
+    b = T.TeukBatch([(w.s, w.m, w.a_over_M, _grid(w)) for w in ws], 1)
+    b.set_sweep(T.SWEEP_WIDE2)
+    b.set_launch(8, 512)
+    b.set_fuse(4)
+    fields = [inputs.initial_fields(w) for w in ws]
+    for k, f in enumerate(fields):
+        b.set_initial(k, *f)
+    b.use_graph(8)
+    b.step(13)
+    for k, w in enumerate(ws):
+        single = _run_gpu(w, fields[k], 13)
+        for f in range(4):
+            assert np.array_equal(b.read_field(k, f), single[f]), (k, f)
+    b.close()
+
+
 def test_fuse_rejects_unsupported_shapes():
     w = inputs.C1.with_(n_r=40, n_theta=32, words=4)
     h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 4)
