@@ -294,6 +294,28 @@ def test_autotuned_shape_is_bitwise(words, tmp_path, monkeypatch):
         assert np.array_equal(got[f], ref[f]), f
 
 
+@pytest.mark.parametrize("n_r", [3, 4, 5, 9])
+def test_fused_tiny_radial_grids(n_r):
+    """Fused launches on grids with fewer r* nodes than a segment (one work
+    item that touches both radial boundaries) match single steps bitwise."""
+    w = inputs.C1.with_(n_r=n_r, n_theta=64, rstar_min=95.0, rstar_max=95.0 + 3.0 * n_r, m=2, a_over_M=0.5)
+    fields = inputs.initial_fields(w)
+    ref = _run_gpu(w, fields, 9)
+    for sweep, seg, block, fuse in ((T.SWEEP_WIDE, 4, 256, 2), (T.SWEEP_WIDE, 4, 256, 4),
+                                    (T.SWEEP_WIDE2, 16, 512, 4), (T.SWEEP_WIDE2, 8, 256, 2)):
+        _note("fused tiny grid: n_r=%d sweep=%d segcols=%d block=%d fuse=%d" % (n_r, sweep, seg, block, fuse))
+        h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 1)
+        h.set_sweep(sweep)
+        h.set_launch(seg, block)
+        h.set_fuse(fuse)
+        h.set_initial(*fields)
+        h.step(9)
+        got = h.fields()
+        h.close()
+        for f in range(4):
+            assert np.array_equal(got[f], ref[f]), (sweep, seg, block, fuse, f)
+
+
 def test_fused_fp64_batch_equals_single():
     """An FP64 batch of uneven instances with four steps per launch and runs of
     two columns gives each instance the bits of its own single-step run."""
