@@ -1,6 +1,8 @@
-"""GPU parity at the workloads' full sizes and step counts, against oracle
+"""GPU parity at full sizes: the workloads' full step counts against oracle
 reference data written by tests/golden/make_golden.py (sampled grid points
-plus the exact global maximum, which normalises the relative L-infinity)."""
+plus the exact global maximum, which normalises the relative L-infinity), and
+the headline grid in every precision against a live oracle run on an r* slab
+that holds the domain of dependence of a window around the pulse."""
 import glob
 import json
 import os
@@ -11,6 +13,8 @@ import numpy as np
 import pytest
 
 from paper_1006_0663_amd import inputs, teuk as T
+from oracle import engine
+from parity_util import gpu_ints, to_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -62,3 +66,58 @@ def test_full_size_parity(path, mode, tmp_path, monkeypatch):
     rel = float(worst / maxabs)
     print("  rel Linf over %d sampled points = %.3e (tolerance %.0e)" % (len(pts), rel, TOL[w.words]), flush=True)
     assert rel <= TOL[w.words]
+
+
+WINDOW = [inputs.C2, inputs.C2_DD, inputs.C2_QD]
+
+
+@pytest.mark.parametrize("w", WINDOW, ids=[x.name for x in WINDOW])
+def test_headline_grid_window_parity(w, tmp_path, monkeypatch):
+    """The whole 4096 x 128 headline grid in each precision, in the launch
+    shape the autotuner picks (as bench.py times it), against the oracle on an
+    r* slab around the pulse: after n steps a node depends only on nodes within
+    n of it, so a slab reaching n + 1 nodes beyond the compared window gives
+    the window's exact oracle values (checked on the CPU: identical integers).
+    Relative L-infinity over the window, normalised by the window's largest
+    reference value (the pulse peak lies inside it)."""
+    import mpmath as mp
+    import torch
+    from oracle import kerr
+    from paper_1006_0663_amd import autotune
+    n, half = 8, 4
+    fields = inputs.initial_fields(w)
+    monkeypatch.setenv("TEUK_TUNE_CACHE", str(tmp_path / "cache.json"))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    h = T.Teuk(w.s, w.m, w.a_over_M, T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass,
+                                                 w.angular_order), w.words)
+    h.set_stream(stream.cuda_stream)
+    h.use_graph(100)
+    h.set_initial(*fields)
+    shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream, steps=100)
+    print("window parity %s: tuned shape %s" % (w.name, shape), flush=True)
+    h.set_initial(*fields)
+    h.step(n)
+    got = [h.read_field(c) for c in range(4)]
+    h.close()
+    peak = int(abs(fields[0][..., 0]).sum(axis=0).argmax())
+    lo, hi = peak - half - n - 1, peak + half + n + 1
+    assert 0 < lo and hi < w.n_r - 1
+    with mp.workprec(kerr.WORK_BITS):
+        hr = (mp.mpf(w.rstar_max) - mp.mpf(w.rstar_min)) / (w.n_r - 1)
+        rmin, rmax = mp.mpf(w.rstar_min) + lo * hr, mp.mpf(w.rstar_min) + hi * hr
+    ns = hi - lo + 1
+    slab = w.with_(n_r=ns)
+    out = engine.run_problem(to_problem(slab, rstar_min=rmin, rstar_max=rmax), [f[:, lo:hi + 1] for f in fields],
+                             n, processes=16)
+    err, mx = 0, 0
+    for c in range(4):
+        g = gpu_ints(got[c][:, peak - half:peak + half + 1])
+        r = [out[c * ns * w.n_theta + j * ns + i] for j in range(w.n_theta)
+             for i in range(peak - half - lo, peak + half - lo + 1)]
+        err = max(err, max(abs(a - b) for a, b in zip(g, r)))
+        mx = max(mx, max(abs(b) for b in r))
+    rel = err / mx
+    print("  rel Linf over the %d x %d window = %.3e (tolerance %.0e)" % (2 * half + 1, w.n_theta, rel,
+                                                                         TOL[w.words]), flush=True)
+    assert mx > 0 and rel <= TOL[w.words]
