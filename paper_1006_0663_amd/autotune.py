@@ -25,7 +25,7 @@ CANDIDATES = {
     2: [(WIDE, s, b, 1) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12, 16)]
        + [(WIDE, s, 512, 1) for s in (24, 32)]
        + [(SEGMENT, 2, 0, 1), (SEGMENT, 2, 128, 1)]
-       + [(WIDE, s, b, 2) for b in (256, 512) for s in (2, 4)],
+       + [(WIDE, s, b, 2) for b in (256, 512) for s in (2, 4)] + [(WIDE, s, 512, 4) for s in (4, 8)],
     4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12, 16)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)],
 }
 
