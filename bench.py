@@ -43,6 +43,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # changes since were host-side or did not alter the generated kernels.)
 MEASURED = {
     "source": "a95add959460", "fetch_scale": 2.0, "write_scale": 1.0,
+    # fp64_mix: FP64 VALU instructions per update (ADD, MUL, FMA, TRANS; wave
+    #   instructions x 64 lanes over the updates of a launch), from
+    #   SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64.  Key as fp64_flops_hw.
+    "fp64_mix": {},
     "traffic": {(2, 16, 512, 4): (9886.8, 16384.0),
                 (2, 8, 256, 2): (9592.8, 16384.0), (2, 16, 512, 2): (9598.8, 16384.0),
                 (1, 8, 512, 2): (9469.2, 16384.0), (1, 4, 256, 1): (9378.6, 16384.0),
@@ -75,11 +79,14 @@ def measured(table, key):
 
 
 def kernel_source_digest():
+    """Digest of every library source (kernels, launch code, header)."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("kernels.hpp", "mparith.hpp", "mpdot.hpp"):
-        with open(os.path.join(ROOT, "paper_1006_0663_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1006_0663_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))] + [os.path.join(ROOT, "include", "teuk.h")]
+    for path in files:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode() + b"\0" + fh.read())
     return h.hexdigest()[:12]
 
 
@@ -90,14 +97,26 @@ def _torch():
     return torch
 
 
-def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=None, fixed_shape=None):
+def graph_length(graph, steps):
+    """Steps per captured graph for a timed run of `steps`: the requested
+    length, but no longer than the run, so that the timed steps replay graphs."""
+    return min(graph, steps) if graph else 0
+
+
+def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=None, fixed_shape=None,
+                round_trip=False):
+    """Time `steps` steps after `warmup` untimed ones, in the autotuned (or
+    given) launch shape, with HIP graphs of graph_length(graph, steps) steps
+    captured before the warm-up.  Returns (ms, wall s, fields finite, shape,
+    graph replays in the timed region, steps those replays covered)."""
     from paper_1006_0663_amd import autotune
     g = T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
     h = T.Teuk(w.s, w.m, w.a_over_M, g, w.words)
     h.set_stream(stream.cuda_stream)
     h.set_initial(*fields)
-    if graph:
-        h.use_graph(graph)          # before tuning: candidates are timed as they will run
+    glen = graph_length(graph, steps)
+    if glen:
+        h.use_graph(glen)           # before tuning: candidates are timed as they will run
     if fixed_shape:
         autotune.apply(h, fixed_shape)
         shape = tuple(fixed_shape) + (1,) * (4 - len(fixed_shape))
@@ -105,11 +124,15 @@ def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=Non
         h.set_launch(tile, 0)
         shape = (h.sweep, tile, 0, 1)
     else:
-        shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream, steps=max(20, 2 * graph))[:4]
+        shape = autotune.tune(h, w.words, [(w.n_r, w.n_theta)], torch, stream, steps=max(20, 2 * glen))[:4]
+    if round_trip:
+        h.set_host_round_trip(True)
+    h.prepare_graph()
     h.set_initial(*fields)
     with torch.cuda.stream(stream):
         h.step(warmup)
         torch.cuda.synchronize()
+        r0 = h.graph_replays
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
@@ -118,9 +141,11 @@ def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=Non
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    replays = h.graph_replays - r0
+    gsteps = max(1, glen // shape[3]) * shape[3] if glen else 0
     finite = h.check_finite()
     h.close()
-    return ms, wall, finite, shape
+    return ms, wall, finite, shape, replays, replays * gsteps
 
 
 def cpu_baseline(w, seconds_target=22.0, single_core_seconds=6.0):
@@ -168,6 +193,30 @@ def cpu_baseline(w, seconds_target=22.0, single_core_seconds=6.0):
                             "threads_checked": engine.threads_in_use()}}
 
 
+def issue_ceiling(name, shape, pct_hw):
+    """Share of the FP64 peak a kernel could reach with every VALU issue slot
+    holding one of its FP64 instructions (the peak counts an FMA as two
+    operations, an ADD or MUL as one): from its measured instruction mix."""
+    mix = measured("fp64_mix", (name,) + tuple(shape))
+    if not mix:
+        return {"issue_ceiling_frac": None, "frac_of_issue_ceiling": None, "fp64_instruction_mix": None}
+    add, mul, fma, trans = mix
+    ops, ins = add + mul + 2 * fma + trans, add + mul + fma + trans
+    ceil = ops / (2.0 * ins)
+    return {"issue_ceiling_frac": ceil,
+            "frac_of_issue_ceiling": None if pct_hw is None else pct_hw / 100.0 / ceil,
+            "fp64_instruction_mix": {"add": add, "mul": mul, "fma": fma, "trans": trans,
+                                     "unit": "FP64 VALU lane-instructions per update"}}
+
+
+def fma_probe(T):
+    """Attainable FP64 rate measured now with the library's FMA probe (8
+    independent chains per lane, 4 wavefronts per SIMD)."""
+    tf, ms = T.fp64_fma_probe(8, 256 * 4 * 4 * 64 // 256, 256, 1 << 16)
+    return {"tflops": tf, "ms": ms, "frac_of_spec": tf / FP64_VECTOR_PEAK_TFLOPS,
+            "config": "8 FMA chains per lane, 4 wavefronts per SIMD, 65,536 iterations"}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -210,8 +259,8 @@ def main():
     fields = inputs.initial_fields(w)
     log("bench: timing %s, %d warmup + %d steps" % (w.name, args.warmup, args.steps))
     fixed = tuple(int(x) for x in args.shape.split(",")) if args.shape else None
-    ms, wall, finite, shape = time_single(T, w, fields, args.steps, args.warmup, args.graph, args.tile, torch,
-                                          stream, log, fixed)
+    ms, wall, finite, shape, replays, gsteps = time_single(T, w, fields, args.steps, args.warmup, args.graph,
+                                                           args.tile, torch, stream, log, fixed)
     pts = w.n_r * w.n_theta
     value = pts * args.steps / (ms / 1e3)
     ms_step = ms / args.steps
@@ -233,7 +282,9 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "teukolsky-lw fp64 s=-2 m=2 a/M=0.9 4096x128 r*[-200,800] cfl=%g steps=%d"
                                % (w.cfl, w.steps),
-                   "n_r": w.n_r, "n_theta": w.n_theta, "words": 1, "graph_steps": args.graph,
+                   "n_r": w.n_r, "n_theta": w.n_theta, "words": 1,
+                   "graph_steps": graph_length(args.graph, args.steps), "graph_replays_timed": replays,
+                   "timed_steps_in_graphs": gsteps,
                    "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1], "block": shape[2],
                    "steps_per_launch": shape[3]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -250,22 +301,29 @@ def main():
         "pct_fp64_peak_hw": None if fhw is None else 100.0 * fhw * value / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
         "finite": finite,
         "wall_s_timed": wall,
+        "kernel_source_digest": kernel_source_digest(),
     }
+    out.update(issue_ceiling(w.name, shape, out["pct_fp64_peak_hw"]))
     if not args.headline_only:
+        log("bench: FP64 FMA probe")
+        out["fp64_fma_probe"] = fma_probe(T)
         per = {"fp64-4096x128": {"words": 1, "steps": args.steps, "updates_per_s": value,
                                  "pct_fp64_peak": out["pct_fp64_peak"],
-                                 "pct_fp64_peak_hw": out["pct_fp64_peak_hw"]}}
-        for wx in (inputs.C3, inputs.C3_PARITY, inputs.C4, inputs.C2_DD, inputs.C2_QD):
+                                 "pct_fp64_peak_hw": out["pct_fp64_peak_hw"],
+                                 "issue_ceiling_frac": out["issue_ceiling_frac"],
+                                 "frac_of_issue_ceiling": out["frac_of_issue_ceiling"]}}
+        for wx in (inputs.C1, inputs.C3, inputs.C3_PARITY, inputs.C4, inputs.C2_DD, inputs.C2_QD):
             log("bench: timing %s (%d steps)" % (wx.name, wx.steps))
             fx = inputs.initial_fields(wx)
-            msx, _, fin, shp = time_single(T, wx, fx, wx.steps, min(args.warmup, wx.steps // 10), args.graph,
-                                           args.tile, torch, stream, log)
+            msx, _, fin, shp, rpx, _ = time_single(T, wx, fx, wx.steps, min(args.warmup, wx.steps // 10),
+                                                   args.graph, args.tile, torch, stream, log)
             ups = wx.n_r * wx.n_theta * wx.steps / (msx / 1e3)
             f = opcount.flops_per_update(wx.words)
             fh = measured("fp64_flops_hw", (wx.name,) + tuple(shp))
             per[wx.name] = {"words": wx.words, "steps": wx.steps, "updates_per_s": ups,
                             "ms_per_step": msx / wx.steps, "sweep": ["segment", "wide", "wide2"][shp[0]],
                             "segcols": shp[1], "block": shp[2], "steps_per_launch": shp[3],
+                            "graph_replays_timed": rpx,
                             "fp64_flops_per_update": f,
                             "pct_fp64_peak": 100.0 * f * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
                             "fp64_flops_per_update_hw": fh,
@@ -273,12 +331,33 @@ def main():
                             100.0 * fh * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
                             "hbm_GBs_algorithmic": opcount.bytes_per_update(wx.words) * ups / 1e9,
                             "finite": fin}
+            per[wx.name].update(issue_ceiling(wx.name, shp, per[wx.name]["pct_fp64_peak_hw"]))
         out["per_precision"] = per
+        log("bench: host round trip of the state every step (%s)" % w.name)
+        nrt = min(args.steps, 40)
+        msr, _, finr, _, _, _ = time_single(T, w, fields, nrt, 2, 0, 0, torch, stream, log, fixed_shape=shape,
+                                            round_trip=True)
+        ups_rt = pts * nrt / (msr / 1e3)
+        out["host_round_trip"] = {
+            "workload": w.name, "steps": nrt, "updates_per_s": ups_rt, "ms_per_step": msr / nrt,
+            "resident_over_round_trip": value / ups_rt, "finite": finr,
+            "bytes_per_step_each_way": 4 * 8 * pts,
+            "note": "state copied device->pinned host->device after every step (the per-step transfer "
+                    "design the paper measured first, Sec. 'Implementation Details'); one step per launch, "
+                    "no graphs"}
         out["batched"] = bench_batched(T, inputs, args, torch, stream, log)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def _field_digest(fields):
+    import hashlib
+    h = hashlib.sha1()
+    for f in fields:
+        h.update(f.tobytes())
+    return h.hexdigest()
 
 
 def bench_batched(T, inputs, args, torch, stream, log):
@@ -299,11 +378,13 @@ def bench_batched(T, inputs, args, torch, stream, log):
         bshape = autotune.tune(b, 2, [(w.n_r, w.n_theta) for w in ws], torch, stream, steps=8)[:4]
     if args.graph:
         b.use_graph(args.graph)
+        b.prepare_graph()
     for k, f in enumerate(fields):
         b.set_initial(k, *f)
     pts = sum(w.n_r * w.n_theta for w in ws)
+    nwarm = min(args.warmup, 50)
     with torch.cuda.stream(stream):
-        b.step(min(args.warmup, 50))
+        b.step(nwarm)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -311,6 +392,8 @@ def bench_batched(T, inputs, args, torch, stream, log):
         e1.record(stream)
         torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1)
+    log("bench: reading back the batched results")
+    digest_b = [_field_digest([b.read_field(k, c) for c in range(4)]) for k in range(len(ws))]
     b.close()
     log("bench: plain loop over the same instances")
     hs = []
@@ -324,11 +407,12 @@ def bench_batched(T, inputs, args, torch, stream, log):
             autotune.tune(h, 2, [(w.n_r, w.n_theta)], torch, stream, steps=8)
         if args.graph:
             h.use_graph(args.graph)
+            h.prepare_graph()
         h.set_initial(*f)
         hs.append(h)
     with torch.cuda.stream(stream):
         for h in hs:
-            h.step(min(args.warmup, 50))
+            h.step(nwarm)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -337,6 +421,7 @@ def bench_batched(T, inputs, args, torch, stream, log):
         e1.record(stream)
         torch.cuda.synchronize()
     ms_p = e0.elapsed_time(e1)
+    digest_p = [_field_digest(h.fields()) for h in hs]
     for h in hs:
         h.close()
     f = opcount.flops_per_update(2)
@@ -344,7 +429,11 @@ def bench_batched(T, inputs, args, torch, stream, log):
     return {"instances": len(ws), "steps": steps, "points": pts, "words": 2,
             "batched_updates_per_s": ub,
             "plain_loop_updates_per_s": pts * steps / (ms_p / 1e3),
-            "speedup": ms_p / ms_b, "sweep": bshape[0], "segcols": bshape[1], "block": bshape[2], "steps_per_launch": bshape[3],
+            "speedup": ms_p / ms_b,
+            "batched_equals_loop": digest_b == digest_p,
+            "equality_check": "SHA-1 of all four fields of every instance after warm-up + timed steps, "
+                              "batched vs loop (bitwise)",
+            "sweep": bshape[0], "segcols": bshape[1], "block": bshape[2], "steps_per_launch": bshape[3],
             "batched_pct_fp64_peak": 100.0 * f * ub / (FP64_VECTOR_PEAK_TFLOPS * 1e12)}
 
 

@@ -90,7 +90,10 @@ const char *teuk_last_error(void);
 /* Validate (s, m, a/M, grid, precision) without touching a device.
  * |s| <= 2, |a/M| < 1, n_theta >= 5, n_r >= 3, rstar_min < rstar_max, cfl > 0,
  * angular_order in {2, 10}, precision in {1, 2, 4}; mass must be 1.0, or 0.0
- * with a/M = 0 and rstar_min > 0.  Returns TEUK_OK or TEUK_EINVAL. */
+ * with a/M = 0 and rstar_min > 0.  Returns TEUK_OK, TEUK_EINVAL, or
+ * TEUK_ENOTSUP for grids this build does not take: n_theta > 256, or
+ * 8 * precision * n_r * n_theta >= 2^32 (the kernels address one word plane
+ * of the eight coefficient components with 32-bit offsets). */
 int teuk_validate(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec);
 
 /* Create one instance on the current HIP device: allocates its state and
@@ -103,7 +106,9 @@ int teuk_destroy(teuk_t *h);
 
 /* Copy the four initial fields (interchange layout, n_theta*n_r*p doubles
  * each) to the device; the radial boundary nodes are then set to zero and the
- * step counter to 0.  Synchronous: the host buffers may be reused on return. */
+ * step counter to 0.  Synchronous: the host buffers may be reused on return.
+ * TEUK_ENONFINITE (nothing uploaded) if a word off the radial boundary is
+ * Inf or NaN. */
 int teuk_set_initial(teuk_t *h, const double *phi_re, const double *phi_im, const double *pi_re,
                      const double *pi_im);
 
@@ -118,7 +123,9 @@ int teuk_read_field(teuk_t *h, teuk_field f, double *out);
 double teuk_dt(const teuk_t *h);
 long teuk_steps_done(const teuk_t *h);
 int teuk_words(const teuk_t *h);
-/* Restore the step counter after a checkpoint restart (fields via set_initial). */
+/* Restore the step counter after a checkpoint restart (fields via
+ * set_initial); an observer's next record is then due at the next multiple
+ * of its cadence, and the records it holds are kept. */
 int teuk_set_step_index(teuk_t *h, long n);
 
 /* Run subsequent work on the given hipStream_t (0 = the library's own stream).
@@ -135,7 +142,8 @@ int teuk_check_finite(teuk_t *h, int *ok);
  * at least n_theta: 64, 128 or 256 for the segment sweep, up to 512 (dd)
  * or 1024 (FP64) for the wide sweep (256 for quad-double); 0 = the default.
  * A shape that does not fit (block too large, not enough LDS) returns
- * TEUK_EINVAL and leaves the previous shape in place. */
+ * TEUK_EINVAL and leaves the previous shape in place.  teuk_set_tile keeps
+ * the block size requested before. */
 int teuk_set_tile(teuk_t *h, int segcols);
 int teuk_set_launch(teuk_t *h, int segcols, int block);
 
@@ -172,7 +180,12 @@ int teuk_set_fuse(teuk_t *h, int steps_per_launch);
  * angular weights (which = 2, [2R+1][n_theta][p]).  Order of the eight:
  * s/h b, s W, s/h K_re, s/h K_im, s Ct_re, s Ct_im, s C0_re, s C0_im with
  * s = dt/2 at half nodes and s = dt at nodes.  set_ overwrites them (for
- * stepping-only checks with externally supplied coefficients). */
+ * stepping-only checks with externally supplied coefficients, which the
+ * oracle's parity tests inject).  On an FP64 handle the first set_ switches
+ * the instance from per-point coefficients to stored planes (seeded from its
+ * own coefficients); stored planes have no fused form, so a handle set to
+ * several steps per launch falls back to one.  If the switch fails the handle
+ * is unchanged; a failed upload after it leaves the handle failed. */
 int teuk_get_coefficients(teuk_t *h, int which, double *out);
 int teuk_set_coefficients(teuk_t *h, int which, const double *in);
 
@@ -193,11 +206,60 @@ int teuk_batch_set_tile(teuk_batch_t *b, int segcols);
 int teuk_batch_set_launch(teuk_batch_t *b, int segcols, int block);
 int teuk_batch_set_sweep(teuk_batch_t *b, int sweep);
 int teuk_batch_set_fuse(teuk_batch_t *b, int steps_per_launch);
-/* Capture the step loop in HIP graphs of about `steps_per_graph` steps (0 = off):
- * an even number of launches, so every replay starts from the state buffer it
- * was captured on; steps that do not fill a graph are launched directly. */
+/* Capture the step loop in HIP graphs of max(1, steps_per_graph / k) launches
+ * (k = steps per launch; 0 = off).  One graph is kept per state buffer a
+ * replay can start from, captured at its first use or by prepare_graph;
+ * steps that do not fill a graph are launched directly.  Changing the launch
+ * shape, the stream or the observer drops the graphs. */
 int teuk_batch_use_graph(teuk_batch_t *b, int steps_per_graph);
 int teuk_use_graph(teuk_t *h, int steps_per_graph);
+/* Capture (and instantiate) both graphs now, so that no later teuk_step pays
+ * for it; runs no steps.  No-op when graphs are off. */
+int teuk_prepare_graph(teuk_t *h);
+int teuk_batch_prepare_graph(teuk_batch_t *b);
+/* Graph replays launched since the handle was created. */
+long teuk_graph_replays(const teuk_t *h);
+long teuk_batch_graph_replays(const teuk_batch_t *b);
+
+/* Host round trip (a measurement mode, Sec. "Implementation Details": the
+ * first CUDA design kept the fields on the host and copied them over PCIe
+ * around the step every time step).  With on != 0, after every step the
+ * state of every instance is copied to pinned host memory and back before the
+ * next step; results are unchanged (bitwise), graphs and fused launches are
+ * not used.  on = 0 turns it off again.  TEUK_ENOMEM if the pinned buffer
+ * (one instance's state) cannot be allocated. */
+int teuk_set_host_round_trip(teuk_t *h, int on);
+int teuk_batch_set_host_round_trip(teuk_batch_t *b, int on);
+
+/* Observer time series (Sec. "Kerr Black Hole Tails": the field recorded at a
+ * fixed location over the whole evolution, whose late-time decay is the
+ * paper's result).  Records Phi (real and imaginary part, all words) at
+ * n_points grid points (r* node i[p], theta row j[p]) into a device ring of
+ * `capacity` records, taken after the first launch that reaches or passes the
+ * next multiple of `every` steps since set_initial (with `every` a multiple
+ * of the steps per launch, exactly at those multiples).  A record is
+ * 1 + 2 * words * n_points doubles: the step index (as a double), then for
+ * each point p the words of Re Phi and then of Im Phi.  Recording runs on the
+ * handle's stream inside the step loop (also inside captured graphs) with no
+ * host round trip.  set_initial clears the records.  n_points = 0 removes
+ * the observer.  1 <= n_points <= 1024, every >= 1, capacity >= 1 and
+ * capacity * record length <= 2^28 doubles; otherwise TEUK_EINVAL. */
+int teuk_set_observer(teuk_t *h, int n_points, const int *i, const int *j, int every, long capacity);
+/* Synchronise and copy out the min(held, max_records) most recent records,
+ * oldest first, to out (host, that many records).  *n_out receives their
+ * number, *n_total (if not NULL) the records written since set_initial
+ * (those beyond `capacity` back are overwritten).  TEUK_EINVAL without an
+ * observer. */
+int teuk_read_observer(teuk_t *h, long max_records, double *out, long *n_out, long *n_total);
+
+/* FP64 FMA throughput probe (the device's attainable FP64 vector rate, the
+ * reference for the step kernels' FP64 operation rates): `blocks` x `threads`
+ * lanes each run `chains` (1, 2, 4 or 8) independent FMA chains of `iters`
+ * iterations (a multiple of 8); *tflops receives 2 * chains * iters *
+ * blocks * threads / time, *ms (if not NULL) the time of the timed launch
+ * (after one untimed launch), on a stream of its own.  Returns TEUK_OK,
+ * TEUK_EINVAL (bad sizes; no message is set), TEUK_ENOMEM or TEUK_EDEVICE. */
+int teuk_fp64_fma_probe(int chains, int blocks, int threads, long iters, double *tflops, double *ms);
 
 /* Test hook for the multiword arithmetic itself: out[k] = op(a[k], b[k]) for
  * k < n, each operand `words` doubles (1, 2 or 4), arrays [n][words].

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libteuk.so")
-SOURCES = ["teuk_api.hip", "prec_f64.hip", "prec_dd.hip", "prec_qd.hip", "arith_hooks.hip"]
+SOURCES = ["teuk_api.hip", "prec_f64.hip", "prec_dd.hip", "prec_qd.hip", "arith_hooks.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # kernarg preload: the first kernel arguments arrive in SGPRs at wave launch
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -21,6 +21,9 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t kMaxRowsLds = 40 * 1024;
+constexpr unsigned long long kMaxPlaneDoubles = 1ull << 32;
+constexpr int kMaxObserverPoints = 1024;
+constexpr double kMaxObserverDoubles = 268435456.0;   // 2^28 doubles (2 GiB) of records
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -40,7 +43,6 @@ int validate(int s, int m, double a_over_M, const teuk_grid *g, int prec) {
     if (g->n_theta < 5) return fail(TEUK_EINVAL, "n_theta must be >= 5 (ghost rows reflect up to 5 rows)");
     if (g->n_theta > 256) return fail(TEUK_ENOTSUP, "n_theta > 256 is not supported by this build");
     if (g->n_r < 3) return fail(TEUK_EINVAL, "n_r must be >= 3");
-    if ((long)g->n_r * (long)g->n_theta > (1L << 30)) return fail(TEUK_EINVAL, "grid too large");
     if (!(g->rstar_min < g->rstar_max) || !std::isfinite(g->rstar_min) || !std::isfinite(g->rstar_max))
         return fail(TEUK_EINVAL, "need finite rstar_min < rstar_max");
     if (!(g->cfl > 0.0) || !std::isfinite(g->cfl)) return fail(TEUK_EINVAL, "cfl must be > 0");
@@ -48,6 +50,11 @@ int validate(int s, int m, double a_over_M, const teuk_grid *g, int prec) {
         return fail(TEUK_EINVAL, "angular_order must be 10 or 2");
     if (prec != TEUK_FP64 && prec != TEUK_DD && prec != TEUK_QD)
         return fail(TEUK_EINVAL, "precision must be 1 (FP64), 2 (double-double) or 4 (quad-double)");
+    // The step kernels address a plane (one word of one component) with
+    // 32-bit offsets; the largest array, the eight coefficient components of
+    // `prec` words each, must stay below 2^32 doubles.
+    if (8ull * (unsigned long long)prec * (unsigned long long)g->n_r * (unsigned long long)g->n_theta >= kMaxPlaneDoubles)
+        return fail(TEUK_ENOTSUP, "grid too large: 8 * words * n_r * n_theta must be below 2^32");
     if (g->mass == 0.0) {
         if (a_over_M != 0.0 || !(g->rstar_min > 0.0))
             return fail(TEUK_EINVAL, "flat-space mode (mass 0) needs a/M = 0 and rstar_min > 0");
@@ -76,7 +83,8 @@ struct Instance {
 struct Batch {
     int words = 1;
     std::vector<Instance> inst;
-    int segcols = 8;
+    int seg_req = 8;         // requested r* nodes per work item
+    int segcols = 8;         // in use: seg_req, shortened where the FP64 radial rows exceed their LDS share
     int nt = 64;
     int nt_req = 0;          // requested block size (0 = default for the sweep)
     int sweep_req = -1;      // requested sweep (TEUK_SWEEP_*; -1 = default for the precision)
@@ -93,17 +101,38 @@ struct Batch {
     hipStream_t own_stream = nullptr;
     int sticky = TEUK_OK;
     int graph_steps = 0;
-    int graph_parity = -1;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    // captured step loops, one per state buffer the replay starts from
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    long graph_replays = 0;
+    // host round trip of the state after every step (measurement mode)
+    double *host_state = nullptr;
+    // observer time series of instance 0 (see teuk_set_observer)
+    int obs_n = 0, obs_every = 0;
+    long obs_cap = 0;
+    int *obs_idx = nullptr;          // device: plane index i * n_theta + j per point
+    double *obs_ring = nullptr;      // device: obs_cap records of 1 + 2 W obs_n doubles
+    long long *obs_ctr = nullptr;    // device: steps since set_initial, records written, next step due
 };
 
 void drop_graph(Batch &b) {
-    if (b.gexec) hipGraphExecDestroy(b.gexec);
-    if (b.graph) hipGraphDestroy(b.graph);
-    b.gexec = nullptr;
-    b.graph = nullptr;
-    b.graph_parity = -1;
+    for (int p = 0; p < 2; ++p) {
+        if (b.gexec[p]) hipGraphExecDestroy(b.gexec[p]);
+        if (b.graph[p]) hipGraphDestroy(b.graph[p]);
+        b.gexec[p] = nullptr;
+        b.graph[p] = nullptr;
+    }
+}
+
+void free_observer(Batch &b) {
+    hipFree(b.obs_idx);
+    hipFree(b.obs_ring);
+    hipFree(b.obs_ctr);
+    b.obs_idx = nullptr;
+    b.obs_ring = nullptr;
+    b.obs_ctr = nullptr;
+    b.obs_n = b.obs_every = 0;
+    b.obs_cap = 0;
 }
 
 void free_batch(Batch &b) {
@@ -124,6 +153,9 @@ void free_batch(Batch &b) {
     hipFree(b.d_items);
     b.d_inst = nullptr;
     b.d_items = nullptr;
+    free_observer(b);
+    if (b.host_state) hipHostFree(b.host_state);
+    b.host_state = nullptr;
     if (b.own_stream) hipStreamDestroy(b.own_stream);
     b.own_stream = nullptr;
 }
@@ -235,8 +267,22 @@ int wide_cols(int c0, int c1, int nr, int ns) {
     return e - a + 1 + ((ns > 1 && e == nr - 1) ? ns : 0);
 }
 
-// (Re)build descriptors and the work list; all instances must share `cur`.
-int build_worklist(Batch &b) {
+// (Re)build the launch plan, the descriptors and the work list from the
+// requests (sweep, segment length, block, steps per launch) and the
+// instances; all instances must share `cur`.  Transactional: the plan is
+// worked out on a copy `b` of the requests and new device arrays are filled
+// before anything of the handle `h` changes, so on failure `h` keeps its
+// previous plan and arrays and stays usable.
+int build_worklist(Batch &h) {
+    Batch b;
+    b.words = h.words;
+    b.inst = h.inst;
+    b.seg_req = h.seg_req;
+    b.segcols = h.seg_req;
+    b.nt_req = h.nt_req;
+    b.sweep_req = h.sweep_req;
+    b.fuse = h.fuse;
+    b.no_scalar_rows = h.no_scalar_rows;
     int maxnth = 0;
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     b.sweep = b.sweep_req >= 0 ? b.sweep_req : default_sweep(b.words);
@@ -374,20 +420,32 @@ int build_worklist(Batch &b) {
         for (int gi = 0; gi < hd[k].groups; ++gi) items.push_back({k, gi});
         xcd_order(items, first, items.size() - first);
     }
-    hipFree(b.d_inst);
-    hipFree(b.d_items);
-    b.d_inst = nullptr;
-    b.d_items = nullptr;
-    hipError_t e = hipMalloc((void **)&b.d_inst, hd.size() * sizeof(lwk::InstDev));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(descriptors)");
-    e = hipMalloc((void **)&b.d_items, std::max<size_t>(1, items.size()) * sizeof(lwk::WorkItem));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
-    e = hipMemcpy(b.d_inst, hd.data(), hd.size() * sizeof(lwk::InstDev), hipMemcpyHostToDevice);
+    lwk::InstDev *d_inst = nullptr;
+    lwk::WorkItem *d_items = nullptr;
+    hipError_t e = hipMalloc((void **)&d_inst, hd.size() * sizeof(lwk::InstDev));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_items, std::max<size_t>(1, items.size()) * sizeof(lwk::WorkItem));
+    if (e == hipSuccess) e = hipMemcpy(d_inst, hd.data(), hd.size() * sizeof(lwk::InstDev), hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
-        e = hipMemcpy(b.d_items, items.data(), items.size() * sizeof(lwk::WorkItem), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work list)");
-    b.nitems = (int)items.size();
-    drop_graph(b);
+        e = hipMemcpy(d_items, items.data(), items.size() * sizeof(lwk::WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(d_inst);
+        hipFree(d_items);
+        return hip_fail(e, "descriptors and work list");
+    }
+    // commit (the previous arrays are no longer referenced by queued work:
+    // every caller has waited for the handle's stream, or nothing was queued)
+    hipFree(h.d_inst);
+    hipFree(h.d_items);
+    h.d_inst = d_inst;
+    h.d_items = d_items;
+    h.nitems = (int)items.size();
+    h.sweep = b.sweep;
+    h.segcols = b.segcols;
+    h.nt = b.nt;
+    h.cmode = b.cmode;
+    h.tm = b.tm;
+    h.lds = b.lds;
+    drop_graph(h);
     return TEUK_OK;
 }
 
@@ -525,6 +583,27 @@ int download_planes(Batch &b, const double *dsrc, int nplanes_w, int nr, int nth
     return TEUK_OK;
 }
 
+// Observer counters (see observer_record_kernel) for a run now at `step`:
+// the next record is due at the next multiple of `every`; `clear` also drops
+// the records held.
+int reset_observer(Batch &b, long step, bool clear) {
+    if (b.obs_n <= 0) return TEUK_OK;
+    long long c[3];
+    hipError_t e = hipStreamSynchronize(b.stream);
+    if (e == hipSuccess) e = hipMemcpy(c, b.obs_ctr, sizeof c, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+        c[0] = step;
+        if (clear) c[1] = 0;
+        c[2] = (step / b.obs_every + 1) * (long long)b.obs_every;
+        e = hipMemcpy(b.obs_ctr, c, sizeof c, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "observer counters");
+    }
+    return TEUK_OK;
+}
+
 int set_initial(Batch &b, int k, const double *pr, const double *pim, const double *qr, const double *qim) {
     if (int rc = check_ok(b)) return rc;
     if (k < 0 || k >= (int)b.inst.size()) return fail(TEUK_EINVAL, "instance index out of range");
@@ -533,10 +612,92 @@ int set_initial(Batch &b, int k, const double *pr, const double *pim, const doub
     // all instances of a batch step together: keep them on the same buffer
     int buf = I.cur;
     const double *src[4] = {pr, pim, qr, qim};
+    // refuse non-finite values before anything is uploaded (radial boundary
+    // nodes are overwritten with zero and not checked)
+    const size_t nv = (size_t)I.words * I.plane();
+    for (int c = 0; c < 4; ++c)
+        for (size_t q = 0; q < nv; ++q) {
+            const size_t i = (q / I.words) % (size_t)I.g.n_r;
+            if (i != 0 && i != (size_t)I.g.n_r - 1 && !std::isfinite(src[c][q]))
+                return fail(TEUK_ENONFINITE, "initial field " + std::to_string(c) + " holds Inf or NaN");
+        }
     for (int c = 0; c < 4; ++c)
         if (int rc = upload_field(b, I, c, src[c], buf)) return rc;
     I.steps = 0;
+    if (k == 0) return reset_observer(b, 0, true);
     return TEUK_OK;
+}
+
+// Observer record after a launch that advanced `ns` steps and left its
+// fields in u (one block; see teuk_set_observer).  ctr[0] = steps since
+// set_initial, ctr[1] = records written, ctr[2] = step at which the next
+// record is due.  Every thread reads the counters before the barrier and
+// thread 0 writes them after it; launches on one stream run in order, so
+// the next launch sees the new values (also inside a captured graph).
+__global__ void observer_record_kernel(const double *__restrict__ u, unsigned long long plane, int W, int npts,
+                                       const int *__restrict__ idx, int every, long long cap, double *ring,
+                                       long long *ctr, int ns) {
+    const long long step = ctr[0] + ns, nrec = ctr[1], due = ctr[2];
+    const bool rec = step >= due;
+    if (rec) {
+        const int len = 2 * W * npts;
+        double *r = ring + (size_t)(nrec % cap) * (size_t)(1 + len);
+        if (threadIdx.x == 0) r[0] = (double)step;
+        for (int q = threadIdx.x; q < len; q += blockDim.x) {
+            const int p = q / (2 * W), c = (q / W) % 2, w = q % W;
+            r[1 + q] = u[((size_t)c * W + w) * plane + (size_t)idx[p]];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctr[0] = step;
+        if (rec) {
+            ctr[1] = nrec + 1;
+            ctr[2] = (step / every + 1) * every;
+        }
+    }
+}
+
+// one step-kernel launch of `ns` steps from buffer `parity`, then the
+// observer record if one is set
+hipError_t launch_step(const Batch &b, int parity, int ns) {
+    hipError_t e = step_launch(b, parity, ns);
+    if (e == hipSuccess && b.obs_n > 0) {
+        const Instance &I = b.inst[0];
+        observer_record_kernel<<<1, 256, 0, b.stream>>>(I.u[parity ^ 1], (unsigned long long)I.plane(), b.words,
+                                                        b.obs_n, b.obs_idx, b.obs_every, (long long)b.obs_cap,
+                                                        b.obs_ring, b.obs_ctr, ns);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// launches of a captured step loop: about graph_steps / fuse, at least one
+int graph_launches(const Batch &b) { return b.graph_steps > 0 ? std::max(1, b.graph_steps / b.fuse) : 0; }
+
+// capture the step loop that starts from state buffer `par`
+hipError_t capture_graph(Batch &b, int par) {
+    const int nl = graph_launches(b);
+    hipError_t e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int q = 0; q < nl && e == hipSuccess; ++q) e = launch_step(b, (par + q) & 1, b.fuse);
+    const hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph[par]);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b.gexec[par], b.graph[par], nullptr, nullptr, 0);
+    return e;
+}
+
+// Host round trip (measurement mode): the state of every instance goes to
+// host memory and back after each step, as a design that keeps the fields on
+// the host and offloads the step would move them.
+hipError_t round_trip(const Batch &b, int buf) {
+    hipError_t e = hipSuccess;
+    for (const Instance &I : b.inst) {
+        const size_t bytes = 4 * (size_t)I.words * I.plane() * sizeof(double);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.host_state, I.u[buf], bytes, hipMemcpyDeviceToHost, b.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(I.u[buf], b.host_state, bytes, hipMemcpyHostToDevice, b.stream);
+    }
+    return e;
 }
 
 int do_steps(Batch &b, long n) {
@@ -546,42 +707,40 @@ int do_steps(Batch &b, long n) {
     long left = n;
     hipError_t e = hipSuccess;
     // a launch advances `fuse` steps (the remainder goes one step per launch);
-    // a captured graph holds about graph_steps / fuse launches, an even number
-    // of them, so that every replay starts from the buffer it was captured on
+    // a captured graph holds graph_launches(b) launches, and one graph is kept
+    // per state buffer a replay can start from
     const int F = b.fuse;
-    int glaunches = b.graph_steps / F;
-    if (b.graph_steps > 0 && glaunches % 2) glaunches = glaunches > 1 ? glaunches - 1 : 2;
-    const int gsteps = glaunches * F;
-    if (glaunches > 0 && left >= gsteps) {
-        if (!b.gexec || b.graph_parity != cur) {
-            drop_graph(b);
-            e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                for (int q = 0; q < glaunches && e == hipSuccess; ++q) e = step_launch(b, (cur + q) & 1, F);
-                hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
-                if (e == hipSuccess) e = e2;
-            }
-            if (e == hipSuccess) e = hipGraphInstantiate(&b.gexec, b.graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                b.sticky = TEUK_EDEVICE;
-                drop_graph(b);
-                return hip_fail(e, "graph capture");
-            }
-            b.graph_parity = cur;
+    if (b.host_state) {
+        for (; left > 0 && e == hipSuccess; --left) {
+            e = launch_step(b, cur, 1);
+            cur ^= 1;
+            if (e == hipSuccess) e = round_trip(b, cur);
         }
-        while (left >= gsteps && e == hipSuccess) {
-            e = hipGraphLaunch(b.gexec, b.stream);
+    } else {
+        const int gl = graph_launches(b);
+        const long gsteps = (long)gl * F;
+        while (gl > 0 && left >= gsteps && e == hipSuccess) {
+            if (!b.gexec[cur]) {
+                e = capture_graph(b, cur);
+                if (e != hipSuccess) {
+                    b.sticky = TEUK_EDEVICE;
+                    drop_graph(b);
+                    return hip_fail(e, "graph capture");
+                }
+            }
+            e = hipGraphLaunch(b.gexec[cur], b.stream);
+            ++b.graph_replays;
             left -= gsteps;
-            cur = (cur + glaunches) & 1;
+            cur = (cur + gl) & 1;
         }
-    }
-    for (; left >= F && e == hipSuccess; left -= F) {
-        e = step_launch(b, cur, F);
-        cur ^= 1;
-    }
-    for (; left > 0 && e == hipSuccess; --left) {
-        e = step_launch(b, cur, 1);
-        cur ^= 1;
+        for (; left >= F && e == hipSuccess; left -= F) {
+            e = launch_step(b, cur, F);
+            cur ^= 1;
+        }
+        for (; left > 0 && e == hipSuccess; --left) {
+            e = launch_step(b, cur, 1);
+            cur ^= 1;
+        }
     }
     if (e != hipSuccess) {
         b.sticky = TEUK_EDEVICE;
@@ -590,6 +749,22 @@ int do_steps(Batch &b, long n) {
     for (auto &I : b.inst) {
         I.cur = cur;
         I.steps += n;
+    }
+    return TEUK_OK;
+}
+
+// capture the step loops of both starting buffers now (no steps run)
+int prepare_graph(Batch &b) {
+    if (int rc = check_ok(b)) return rc;
+    if (b.graph_steps <= 0 || b.host_state) return TEUK_OK;
+    for (int par = 0; par < 2; ++par) {
+        if (b.gexec[par]) continue;
+        const hipError_t e = capture_graph(b, par);
+        if (e != hipSuccess) {
+            b.sticky = TEUK_EDEVICE;
+            drop_graph(b);
+            return hip_fail(e, "graph capture");
+        }
     }
     return TEUK_OK;
 }
@@ -669,8 +844,9 @@ long teuk_steps_done(const teuk_t *h) { return h ? h->b.inst[0].steps : -1; }
 int teuk_words(const teuk_t *h) { return h ? h->b.words : 0; }
 int teuk_set_step_index(teuk_t *h, long n) {
     if (!h || n < 0) return fail(TEUK_EINVAL, "bad handle or step index");
+    if (int rc = check_ok(h->b)) return rc;
     h->b.inst[0].steps = n;
-    return TEUK_OK;
+    return reset_observer(h->b, n, false);
 }
 int teuk_set_stream(teuk_t *h, void *st) {
     if (!h) return fail(TEUK_EINVAL, "handle is NULL");
@@ -682,11 +858,10 @@ int teuk_use_graph(teuk_t *h, int k) {
     h->b.graph_steps = k;
     return TEUK_OK;
 }
+static int set_launch(Batch &b, int segcols, int block);
 int teuk_set_tile(teuk_t *h, int segcols) {
-    if (!h || segcols < 1) return fail(TEUK_EINVAL, "bad handle or tile");
-    if (int rc = quiesce(h->b)) return rc;
-    h->b.segcols = segcols;
-    return build_worklist(h->b);
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_launch(h->b, segcols, h->b.nt_req);
 }
 
 static int set_launch(Batch &b, int segcols, int block) {
@@ -696,19 +871,17 @@ static int set_launch(Batch &b, int segcols, int block) {
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     if (block != 0 && block < maxnth) return fail(TEUK_EINVAL, "block must be >= n_theta");
     if (int rc = quiesce(b)) return rc;
-    const int old_seg = b.segcols, old_nt = b.nt_req;
-    b.segcols = segcols;
+    const int old_seg = b.seg_req, old_nt = b.nt_req;
+    b.seg_req = segcols;
     b.nt_req = block;
-    int rc = build_worklist(b);
+    const int rc = build_worklist(b);
     if (rc != TEUK_OK) {
-        // keep the handle usable with its previous shape
-        b.segcols = old_seg;
+        // the handle keeps its previous plan (build_worklist changes nothing
+        // on failure); restore the requests that plan was built from
+        b.seg_req = old_seg;
         b.nt_req = old_nt;
-        const std::string msg = g_err;
-        build_worklist(b);
-        return fail(rc, msg);
     }
-    return TEUK_OK;
+    return rc;
 }
 
 static int set_sweep(Batch &b, int sweep) {
@@ -720,15 +893,12 @@ static int set_sweep(Batch &b, int sweep) {
     const int old = b.sweep_req, old_nt = b.nt_req;
     b.sweep_req = sweep;
     b.nt_req = 0;
-    int rc = build_worklist(b);
+    const int rc = build_worklist(b);
     if (rc != TEUK_OK) {
         b.sweep_req = old;
         b.nt_req = old_nt;
-        const std::string msg = g_err;
-        build_worklist(b);
-        return fail(rc, msg);
     }
-    return TEUK_OK;
+    return rc;
 }
 
 int teuk_set_sweep(teuk_t *h, int sweep) {
@@ -746,14 +916,9 @@ static int set_fuse(Batch &b, int ns) {
     if (int rc = quiesce(b)) return rc;
     const int old = b.fuse;
     b.fuse = ns;
-    int rc = build_worklist(b);
-    if (rc != TEUK_OK) {
-        b.fuse = old;
-        const std::string msg = g_err;
-        build_worklist(b);
-        return fail(rc, msg);
-    }
-    return TEUK_OK;
+    const int rc = build_worklist(b);
+    if (rc != TEUK_OK) b.fuse = old;
+    return rc;
 }
 int teuk_set_fuse(teuk_t *h, int steps_per_launch) {
     if (!h) return fail(TEUK_EINVAL, "handle is NULL");
@@ -833,18 +998,41 @@ int teuk_get_coefficients(teuk_t *h, int which, double *out) {
 int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
     if (!h || !in || which < 0 || which > 1) return fail(TEUK_EINVAL, "bad arguments");
     Batch &b = h->b;
-    if (int rc = check_ok(b)) return rc;
+    if (int rc = quiesce(b)) return rc;
     Instance &I = b.inst[0];
     const int W = I.words, nth = I.g.n_theta;
     if (I.onfly) {
-        // switch this instance to stored planes, seeded from its own per-point coefficients
-        hipError_t e = hipMalloc((void **)&I.cf, 8 * (size_t)I.g.n_r * nth * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc((void **)&I.ch, 8 * (size_t)(I.g.n_r - 1) * nth * sizeof(double));
-        if (e == hipSuccess) e = lwk::fp64_planes(I.g.n_r, nth, I.rf, I.rh, I.trig, I.cf, I.ch, b.stream);
+        // switch this instance to stored planes, seeded from its own per-point
+        // coefficients.  Stored planes have no fused form: a handle set to
+        // several steps per launch falls back to one.  Nothing of the handle
+        // changes unless the new plan is in place.
+        double *cf = nullptr, *ch = nullptr;
+        hipError_t e = hipMalloc((void **)&cf, 8 * (size_t)I.g.n_r * nth * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void **)&ch, 8 * (size_t)(I.g.n_r - 1) * nth * sizeof(double));
+        if (e == hipSuccess) e = lwk::fp64_planes(I.g.n_r, nth, I.rf, I.rh, I.trig, cf, ch, b.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
-        if (e != hipSuccess) return hip_fail(e, "coefficient planes");
+        if (e != hipSuccess) {
+            hipFree(cf);
+            hipFree(ch);
+            return hip_fail(e, "coefficient planes");
+        }
+        I.cf = cf;
+        I.ch = ch;
         I.onfly = 0;
-        if (int rc = build_worklist(b)) return rc;
+        const int old_fuse = b.fuse;
+        int rc = build_worklist(b);
+        if (rc != TEUK_OK && b.fuse > 1) {
+            b.fuse = 1;
+            rc = build_worklist(b);
+        }
+        if (rc != TEUK_OK) {
+            b.fuse = old_fuse;
+            I.onfly = 1;
+            I.cf = I.ch = nullptr;
+            hipFree(cf);
+            hipFree(ch);
+            return rc;
+        }
     }
     const int nr = which == 0 ? I.g.n_r - 1 : I.g.n_r;
     double *dst = which == 0 ? I.ch : I.cf;
@@ -858,7 +1046,10 @@ int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
         hipError_t e = hipMemcpyAsync(dst + (size_t)c * W * plane, tmp.data(), tmp.size() * sizeof(double),
                                       hipMemcpyHostToDevice, b.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
-        if (e != hipSuccess) return hip_fail(e, "set coefficients");
+        if (e != hipSuccess) {
+            b.sticky = TEUK_EDEVICE;     // the planes are partly overwritten
+            return hip_fail(e, "set coefficients");
+        }
     }
     return TEUK_OK;
 }
@@ -907,15 +1098,118 @@ double teuk_batch_dt(const teuk_batch_t *b, int k) {
     return (b && k >= 0 && k < (int)b->b.inst.size()) ? b->b.inst[k].dt_lead : 0.0;
 }
 int teuk_batch_set_tile(teuk_batch_t *b, int segcols) {
-    if (!b || segcols < 1) return fail(TEUK_EINVAL, "bad handle or tile");
-    if (int rc = quiesce(b->b)) return rc;
-    b->b.segcols = segcols;
-    return build_worklist(b->b);
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_launch(b->b, segcols, b->b.nt_req);
 }
 int teuk_batch_use_graph(teuk_batch_t *b, int k) {
     if (!b || k < 0) return fail(TEUK_EINVAL, "bad handle or graph length");
     drop_graph(b->b);
     b->b.graph_steps = k;
+    return TEUK_OK;
+}
+
+int teuk_prepare_graph(teuk_t *h) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return prepare_graph(h->b);
+}
+int teuk_batch_prepare_graph(teuk_batch_t *b) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return prepare_graph(b->b);
+}
+long teuk_graph_replays(const teuk_t *h) { return h ? h->b.graph_replays : -1; }
+long teuk_batch_graph_replays(const teuk_batch_t *b) { return b ? b->b.graph_replays : -1; }
+
+static int set_round_trip(Batch &b, int on) {
+    if (int rc = quiesce(b)) return rc;
+    if (!on) {
+        if (b.host_state) hipHostFree(b.host_state);
+        b.host_state = nullptr;
+        return TEUK_OK;
+    }
+    if (b.host_state) return TEUK_OK;
+    size_t bytes = 0;
+    for (const Instance &I : b.inst) bytes = std::max(bytes, 4 * (size_t)I.words * I.plane() * sizeof(double));
+    const hipError_t e = hipHostMalloc((void **)&b.host_state, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        b.host_state = nullptr;
+        return hip_fail(e, "hipHostMalloc(round-trip buffer)");
+    }
+    drop_graph(b);
+    return TEUK_OK;
+}
+int teuk_set_host_round_trip(teuk_t *h, int on) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_round_trip(h->b, on);
+}
+int teuk_batch_set_host_round_trip(teuk_batch_t *b, int on) {
+    if (!b) return fail(TEUK_EINVAL, "handle is NULL");
+    return set_round_trip(b->b, on);
+}
+
+int teuk_set_observer(teuk_t *h, int n_points, const int *i, const int *j, int every, long capacity) {
+    if (!h) return fail(TEUK_EINVAL, "handle is NULL");
+    Batch &b = h->b;
+    const Instance &I = b.inst[0];
+    if (n_points < 0 || n_points > kMaxObserverPoints)
+        return fail(TEUK_EINVAL, "n_points must be 0..1024");
+    if (n_points > 0) {
+        if (!i || !j) return fail(TEUK_EINVAL, "point index array is NULL");
+        for (int p = 0; p < n_points; ++p)
+            if (i[p] < 0 || i[p] >= I.g.n_r || j[p] < 0 || j[p] >= I.g.n_theta)
+                return fail(TEUK_EINVAL, "observer point outside the grid");
+        if (every < 1) return fail(TEUK_EINVAL, "every must be >= 1");
+        const double doubles = (double)capacity * (1.0 + 2.0 * b.words * n_points);
+        if (capacity < 1 || doubles > kMaxObserverDoubles)
+            return fail(TEUK_EINVAL, "capacity must be >= 1 and hold at most 2^28 doubles of records");
+    }
+    if (int rc = quiesce(b)) return rc;
+    free_observer(b);
+    drop_graph(b);
+    if (n_points == 0) return TEUK_OK;
+    std::vector<int> idx(n_points);
+    for (int p = 0; p < n_points; ++p) idx[p] = i[p] * I.g.n_theta + j[p];
+    const size_t rec = 1 + 2 * (size_t)b.words * n_points;
+    hipError_t e = hipMalloc((void **)&b.obs_idx, n_points * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&b.obs_ring, (size_t)capacity * rec * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&b.obs_ctr, 3 * sizeof(long long));
+    if (e == hipSuccess) e = hipMemcpy(b.obs_idx, idx.data(), n_points * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_observer(b);
+        return hip_fail(e, "observer buffers");
+    }
+    b.obs_n = n_points;
+    b.obs_every = every;
+    b.obs_cap = capacity;
+    return reset_observer(b, I.steps, true);
+}
+
+int teuk_read_observer(teuk_t *h, long max_records, double *out, long *n_out, long *n_total) {
+    if (!h || max_records < 0 || (max_records > 0 && !out)) return fail(TEUK_EINVAL, "bad arguments");
+    Batch &b = h->b;
+    if (int rc = check_ok(b)) return rc;
+    if (b.obs_n <= 0) return fail(TEUK_EINVAL, "no observer is set");
+    long long c[3];
+    hipError_t e = hipStreamSynchronize(b.stream);
+    if (e == hipSuccess) e = hipMemcpy(c, b.obs_ctr, sizeof c, hipMemcpyDeviceToHost);
+    const size_t rec = 1 + 2 * (size_t)b.words * b.obs_n;
+    const long held = (long)std::min<long long>(c[1], b.obs_cap);
+    const long n = std::min(held, max_records);
+    // the n most recent records, oldest first: records c[1]-n .. c[1]-1, which
+    // sit in ring slots q0 .. q0+n-1 (mod capacity): at most two copies
+    if (e == hipSuccess && n > 0) {
+        const long long q0 = (c[1] - n) % b.obs_cap;
+        const long first = (long)std::min<long long>(n, b.obs_cap - q0);
+        e = hipMemcpy(out, b.obs_ring + (size_t)q0 * rec, (size_t)first * rec * sizeof(double), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && first < n)
+            e = hipMemcpy(out + (size_t)first * rec, b.obs_ring, (size_t)(n - first) * rec * sizeof(double),
+                          hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "read observer");
+    }
+    if (n_out) *n_out = n;
+    if (n_total) *n_total = (long)c[1];
     return TEUK_OK;
 }
 

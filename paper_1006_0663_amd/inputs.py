@@ -2,9 +2,15 @@
 
 This module is shared by the tests, the benchmark and the oracle's drivers.
 It holds none of the scheme's arithmetic: only the workload descriptions,
-the seeded random draws and the initial data, a Gaussian pulse in r* times
-sin^4(theta) with momentum Pi = 0.  The paper runs from compactly supported
-data it does not specify (caption of Fig. 1); these pulses stand in for it.
+the seeded random draws and the initial data, with momentum Pi = 0 and one of
+two profiles:
+
+* "gauss_sin4": a Gaussian pulse in r* times sin^4(theta);
+* "bump_legendre": a compactly supported bump (1 - x^2)^8, x = (r* - r0)/w,
+  w = 4 sigma, times the associated Legendre function P_l^|m|(cos theta) of
+  one multipole l (spin weight 0 only).  The paper's tail run (caption of
+  Fig. 1) starts from compactly supported l = 0 data of a scalar field
+  (Sec. "Teukolsky Equation": s = 0); these stand in for it.
 
 Initial values are computed exactly enough to be *defined* by this module:
 the Gaussian factor, sin^4 and the amplitude are evaluated at 450 bits,
@@ -44,6 +50,8 @@ class Workload:
     angular_order: int = 10
     amplitude: str = "phase"        # "phase": exp(i phi0); "normal": (x + i y) scaled to max |Phi| = 1
     seed: int = 0
+    profile: str = "gauss_sin4"     # or "bump_legendre" (s = 0)
+    ell: int = 0                    # multipole of "bump_legendre" (ell >= |m|)
 
     def with_(self, **kw):
         return replace(self, **kw)
@@ -81,6 +89,28 @@ WORKLOADS = {w.name: w for w in (C1, C2, C3, C3_PARITY, C4, C2_DD, C2_QD)}
 BATCH_RSTAR = (-200.0, 800.0)
 BATCH_NR = (1024, 2048, 4096, 8192)
 BATCH_NTH = (32, 64, 128, 256)
+
+
+# Spin weight 0 (the paper's own field, Sec. "Teukolsky Equation") with
+# l-projected compactly supported data: the late-time tail workloads.  a = 0
+# (Schwarzschild), where Price's law fixes the decay at a fixed radius to
+# t^-(2l+3); the grid keeps reflections from both Dirichlet ends away from the
+# observer (r* = 30) until t ~ 1,260 M.  dt = 0.3 dtheta (the s = 0, m = 0
+# angular operator has no pole term).
+TAIL_RSTAR = (-600.0, 1000.0)
+S0_L0 = Workload("s0-l0-dd-3201x16", s=0, m=0, a_over_M=0.0, n_r=3201, n_theta=16, rstar_min=TAIL_RSTAR[0],
+                 rstar_max=TAIL_RSTAR[1], words=2, steps=18000, cfl=0.3, profile="bump_legendre", ell=0)
+S0_L1 = S0_L0.with_(name="s0-l1-dd-3201x16", ell=1)
+# rotating hole, s = 0, l = 2 data (spheroidal mode coupling): parity sizes
+S0_KERR = Workload("s0-l2-m1-a0.9", s=0, m=1, a_over_M=0.9, n_r=1024, n_theta=32, rstar_min=-200.0,
+                   rstar_max=800.0, words=2, steps=2000, cfl=0.3, profile="bump_legendre", ell=2)
+TAIL_PULSE_R0, TAIL_PULSE_SIGMA = 50.0, 5.0
+WORKLOADS.update({w.name: w for w in (S0_L0, S0_L1, S0_KERR)})
+
+
+def tail_pulse():
+    """The pulse of the tail workloads: centred at r* = 50 M, half-width 20 M, amplitude 1."""
+    return Pulse(TAIL_PULSE_R0, TAIL_PULSE_SIGMA, mp.mpf(1), mp.mpf(0))
 
 
 def batch_workloads(n: int = 32, seed: int = 0, steps: int = 2000, words: int = 2, cfl: float = LONG_RUN_CFL):
@@ -135,12 +165,19 @@ def _int_to_words(X: int, scale_bits: int, words: int):
 def initial_fields(w: Workload, pulse: Pulse = None):
     """(phi_re, phi_im, pi_re, pi_im), each float64 [n_theta][n_r][words].
 
-    Phi(0) = A exp(-(r* - r0)^2 / (2 sigma^2)) sin^4(theta), Pi(0) = 0, with the
-    radial boundary columns zero.  For amplitude "normal" the field is scaled
-    so that its largest modulus on the grid is 1.
+    Phi(0) = A f(r*) Y(theta), Pi(0) = 0, with the radial boundary columns
+    zero: f = exp(-(r* - r0)^2 / (2 sigma^2)) and Y = sin^4(theta) for the
+    profile "gauss_sin4"; f = (1 - x^2)^8 on |x| < 1 (0 elsewhere),
+    x = (r* - r0)/(4 sigma), and Y = P_l^|m|(cos theta) for "bump_legendre".
+    For amplitude "normal" the field is scaled so that its largest modulus on
+    the grid is 1.
     """
     if pulse is None:
         pulse = draw_pulse(w)
+    if w.profile not in ("gauss_sin4", "bump_legendre"):
+        raise ValueError("unknown profile %r" % w.profile)
+    if w.profile == "bump_legendre" and (w.s != 0 or w.ell < abs(w.m)):
+        raise ValueError("l-projected data are built for s = 0 and l >= |m|")
     nr, nth, p = w.n_r, w.n_theta, w.words
     with mp.workprec(450):
         h = (mp.mpf(w.rstar_min) * -1 + w.rstar_max) / (nr - 1)
@@ -148,13 +185,20 @@ def initial_fields(w: Workload, pulse: Pulse = None):
         g = []
         for i in range(nr):
             x = mp.mpf(w.rstar_min) + i * h
-            v = mp.exp(-(x - r0) ** 2 / (2 * sg * sg))
+            if w.profile == "gauss_sin4":
+                v = mp.exp(-(x - r0) ** 2 / (2 * sg * sg))
+            else:
+                y = (x - r0) / (4 * sg)
+                v = (1 - y * y) ** 8 if abs(y) < 1 else mp.mpf(0)
             g.append(v if (v >= _FLUSH and 0 < i < nr - 1) else mp.mpf(0))
         k = mp.pi / nth
-        t = [mp.sin((j + mp.mpf(1) / 2) * k) ** 4 for j in range(nth)]
+        if w.profile == "gauss_sin4":
+            t = [mp.sin((j + mp.mpf(1) / 2) * k) ** 4 for j in range(nth)]
+        else:
+            t = [mp.legenp(w.ell, abs(w.m), mp.cos((j + mp.mpf(1) / 2) * k)) for j in range(nth)]
         are, aim = pulse.amp_re, pulse.amp_im
         if w.amplitude == "normal":
-            peak = max(g) * max(t)
+            peak = max(g) * max(abs(v) for v in t)
             are, aim = are / peak, aim / peak
         G = [int(mp.nint(mp.ldexp(v, _K))) for v in g]
         T = [int(mp.nint(mp.ldexp(v, _K))) for v in t]

@@ -74,6 +74,17 @@ _SIGS = {
     "teuk_batch_set_tile": ([_P, ctypes.c_int], ctypes.c_int),
     "teuk_batch_use_graph": ([_P, ctypes.c_int], ctypes.c_int),
     "teuk_use_graph": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_prepare_graph": ([_P], ctypes.c_int),
+    "teuk_batch_prepare_graph": ([_P], ctypes.c_int),
+    "teuk_graph_replays": ([_P], ctypes.c_long),
+    "teuk_batch_graph_replays": ([_P], ctypes.c_long),
+    "teuk_set_host_round_trip": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_batch_set_host_round_trip": ([_P, ctypes.c_int], ctypes.c_int),
+    "teuk_set_observer": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                           ctypes.c_int, ctypes.c_long], ctypes.c_int),
+    "teuk_read_observer": ([_P, ctypes.c_long, _D, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)],
+                           ctypes.c_int),
+    "teuk_fp64_fma_probe": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, _D, _D], ctypes.c_int),
     "teuk_arith_host": ([ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_int], ctypes.c_int),
     "teuk_arith_device": ([ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_int], ctypes.c_int),
 }
@@ -188,6 +199,35 @@ class Teuk:
     def set_sweep(self, sweep):
         _check(lib().teuk_set_sweep(self.h, int(sweep)))
 
+    def prepare_graph(self):
+        _check(lib().teuk_prepare_graph(self.h))
+
+    @property
+    def graph_replays(self):
+        return lib().teuk_graph_replays(self.h)
+
+    def set_host_round_trip(self, on):
+        _check(lib().teuk_set_host_round_trip(self.h, int(bool(on))))
+
+    def set_observer(self, points, every=1, capacity=1 << 16):
+        """points: sequence of (i, j) grid indices (r* node, theta row); [] removes the observer."""
+        n = len(points)
+        ii = (ctypes.c_int * max(n, 1))(*[int(p[0]) for p in points])
+        jj = (ctypes.c_int * max(n, 1))(*[int(p[1]) for p in points])
+        _check(lib().teuk_set_observer(self.h, n, ii, jj, int(every), int(capacity)))
+        self._obs = (n, int(capacity))
+
+    def read_observer(self, max_records=None):
+        """(steps [n], phi [n][points][2][words], records written since set_initial)."""
+        npts, cap = self._obs
+        k = cap if max_records is None else int(max_records)
+        rec = 1 + 2 * self.words * npts
+        out = np.empty((max(k, 1), rec))
+        n_out, n_tot = ctypes.c_long(0), ctypes.c_long(0)
+        _check(lib().teuk_read_observer(self.h, k, _dptr(out), ctypes.byref(n_out), ctypes.byref(n_tot)))
+        out = out[:n_out.value]
+        return out[:, 0].astype(np.int64), out[:, 1:].reshape(-1, npts, 2, self.words), n_tot.value
+
     @property
     def sweep(self):
         return lib().teuk_get_sweep(self.h)
@@ -280,6 +320,16 @@ class TeukBatch:
     def use_graph(self, k):
         _check(lib().teuk_batch_use_graph(self.h, int(k)))
 
+    def prepare_graph(self):
+        _check(lib().teuk_batch_prepare_graph(self.h))
+
+    @property
+    def graph_replays(self):
+        return lib().teuk_batch_graph_replays(self.h)
+
+    def set_host_round_trip(self, on):
+        _check(lib().teuk_batch_set_host_round_trip(self.h, int(bool(on))))
+
 
 def arith(words, op, a, b, device=False):
     """Apply one multiword operation to arrays a, b of shape [n][words]."""
@@ -289,3 +339,13 @@ def arith(words, op, a, b, device=False):
     f = lib().teuk_arith_device if device else lib().teuk_arith_host
     _check(f(words, op, _dptr(a), _dptr(b), _dptr(out), a.shape[0]))
     return out
+
+
+def fp64_fma_probe(chains, blocks, threads, iters):
+    """(TFLOP/s, ms) of the FP64 FMA probe kernel (see teuk_fp64_fma_probe)."""
+    tf, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().teuk_fp64_fma_probe(int(chains), int(blocks), int(threads), int(iters), ctypes.byref(tf),
+                                   ctypes.byref(ms))
+    if rc != TEUK_OK:
+        raise TeukError(rc, "fp64 FMA probe failed")
+    return tf.value, ms.value

@@ -34,7 +34,7 @@ def _int_words(X, words=4):
 
 
 def workloads():
-    out = {w.name: w for w in (inputs.C1, inputs.C3_PARITY, inputs.C4, inputs.C2)}
+    out = {w.name: w for w in (inputs.C1, inputs.C3_PARITY, inputs.C4, inputs.C2, inputs.S0_KERR)}
     batch = inputs.batch_workloads()
     small = sorted(batch, key=lambda w: w.n_r * w.n_theta)[:2]
     for w in small:

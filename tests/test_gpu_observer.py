@@ -1,0 +1,134 @@
+"""Observer time series (Sec. "Kerr Black Hole Tails"): the field recorded at
+fixed grid points during the run, inside the step loop.
+
+* parity: every record equals the oracle's value at that point and step, to
+  the precision's tolerance relative to the oracle field's maximum then;
+* Price's law: from compactly supported l = 0 and l = 1 scalar (s = 0) data
+  on a Schwarzschild background, Phi at a fixed radius decays as
+  t^-(2l+3) at late times; a double-double run fits the exponent within 5 %.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import engine, problem
+from paper_1006_0663_amd import inputs, teuk as T
+from parity_util import to_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {1: 1e-12, 2: 1e-28, 4: 1e-60}
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _grid(w):
+    return T.make_grid(w.n_r, w.n_theta, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order)
+
+
+def oracle_series(w, fields, nsteps, points):
+    """Per step k = 1..nsteps: ([(Re Phi, Im Phi) ints per point], max |value| over the fields)."""
+    tab = problem.build_tables(to_problem(w))
+    FT = engine.tables_to_fixed(tab)
+    u = engine.fields_to_fixed(fields)
+    n = w.n_r * w.n_theta
+    out = []
+    for _ in range(nsteps):
+        u = engine.run_fixed(FT, w.n_r, w.n_theta, u, 1)
+        vals = [(u[0 * n + j * w.n_r + i], u[1 * n + j * w.n_r + i]) for i, j in points]
+        out.append((vals, max(abs(v) for v in u)))
+    return out
+
+
+PARITY = [
+    ("s0-l2-m1-a0.9-fp64", inputs.S0_KERR.with_(n_r=41, n_theta=12, rstar_min=60.0, rstar_max=150.0, words=1), 1, 1),
+    ("s0-l2-m1-a0.9-dd", inputs.S0_KERR.with_(n_r=41, n_theta=12, rstar_min=60.0, rstar_max=150.0), 1, 1),
+    ("s0-l2-m1-a0.9-dd-fused", inputs.S0_KERR.with_(n_r=45, n_theta=32, rstar_min=60.0, rstar_max=150.0), 2, 2),
+    ("s0-l1-m0-a0.5-qd", inputs.S0_KERR.with_(n_r=37, n_theta=10, rstar_min=70.0, rstar_max=140.0, m=0, ell=1,
+                                              a_over_M=0.5, words=4), 1, 1),
+    ("s-2-gauss-fp64-fused", inputs.C1.with_(n_r=47, n_theta=64, rstar_min=60.0, rstar_max=150.0, m=1,
+                                             a_over_M=0.8), 4, 4),
+]
+
+
+@pytest.mark.parametrize("label,w,every,fuse", PARITY, ids=[x[0] for x in PARITY])
+def test_observer_series_matches_oracle(label, w, every, fuse):
+    nsteps = 12
+    fields = inputs.initial_fields(w)
+    peak = int(abs(fields[0][..., 0]).sum(axis=0).argmax())
+    points = [(peak, 2), (peak + 3, w.n_theta - 1), (0, 0), (w.n_r - 2, w.n_theta // 2)]
+    _note("observer %s: %dx%d words=%d every=%d fuse=%d" % (label, w.n_r, w.n_theta, w.words, every, fuse))
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), w.words)
+    if fuse > 1:
+        h.set_sweep(T.SWEEP_WIDE2 if w.words == 1 else T.SWEEP_WIDE)
+        h.set_launch(8, 512)
+        h.set_fuse(fuse)
+    h.use_graph(4)
+    h.set_observer(points, every=every, capacity=64)
+    h.set_initial(*fields)
+    h.step(nsteps)
+    steps, phi, total = h.read_observer()
+    assert h.graph_replays >= 1
+    assert total == nsteps // every and list(steps) == list(range(every, nsteps + 1, every))
+    ref = oracle_series(w, fields, nsteps, points)
+    worst = 0.0
+    for r, k in enumerate(steps):
+        vals, mx = ref[k - 1]
+        for p in range(len(points)):
+            for c in range(2):
+                g = engine.words_to_fixed(phi[r, p, c])
+                worst = max(worst, abs(g - vals[p][c]) / mx)
+    _note("  worst |gpu - oracle| / max|oracle| over %d records = %.3e" % (len(steps), worst))
+    assert worst <= TOL[w.words]
+    assert np.all(phi[:, 2] == 0)                      # the radial boundary node stays zero
+    # set_initial clears the records; a capacity smaller than the run keeps the latest
+    h.set_observer(points, every=every, capacity=2)
+    h.set_initial(*fields)
+    h.step(nsteps)
+    steps2, phi2, total2 = h.read_observer()
+    assert total2 == nsteps // every and list(steps2) == list(steps[-2:])
+    assert np.array_equal(phi2, phi[-2:])
+    h.close()
+
+
+TAILS = [inputs.S0_L0, inputs.S0_L1]
+
+
+@pytest.mark.parametrize("w", TAILS, ids=[x.name for x in TAILS])
+def test_price_law_tail(w):
+    """l-projected compact data, s = 0, a = 0: the late-time decay of Phi at
+    r* = 30 M follows t^-(2l+3) (Price's law).  Least-squares slope of
+    ln|Phi| against ln t over 400 M <= t <= 1000 M, before reflections from
+    either Dirichlet boundary can reach the observer (t ~ 1,260 M)."""
+    fields = inputs.initial_fields(w, inputs.tail_pulse())
+    hr = (w.rstar_max - w.rstar_min) / (w.n_r - 1)
+    i_obs = int(round((30.0 - w.rstar_min) / hr))
+    j_obs = 2
+    every = 4
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), w.words)
+    h.use_graph(400)
+    h.set_observer([(i_obs, j_obs)], every=every, capacity=w.steps // every)
+    h.set_initial(*fields)
+    _note("tail %s: %d steps, dt = %.5f, observer r* = %.1f theta row %d" % (w.name, w.steps, h.dt,
+                                                                              w.rstar_min + i_obs * hr, j_obs))
+    h.step(w.steps)
+    steps, phi, total = h.read_observer()
+    h.close()
+    assert total == w.steps // every
+    t = steps * h.dt
+    val = phi[:, 0, 0, :].sum(axis=1)                  # Re Phi (leading words suffice for a fit)
+    assert np.all(phi[:, 0, 1, 0] == 0)                # a = 0 real data stay real
+    sel = (t >= 400.0) & (t <= 1000.0)
+    assert np.all(val[sel] != 0) and (np.all(val[sel] > 0) or np.all(val[sel] < 0))
+    slope = np.polyfit(np.log(t[sel]), np.log(np.abs(val[sel])), 1)[0]
+    want = -(2 * w.ell + 3)
+    # local exponents over the window, for the log
+    loc = [np.log(abs(val[sel][k + 50] / val[sel][k])) / np.log(t[sel][k + 50] / t[sel][k])
+           for k in range(0, sel.sum() - 50, 300)]
+    _note("  fitted exponent %.4f (Price: %d); local exponents %s" % (slope, want,
+                                                                      ", ".join("%.3f" % x for x in loc)))
+    assert abs(slope - want) <= 0.05 * abs(want)

@@ -49,6 +49,19 @@ SMALL = [
     ("dd-m3-a0.99", inputs.C4.with_(n_r=45, n_theta=12, rstar_min=60.0, rstar_max=150.0, m=3, words=2)),
     ("qd-m2-a0.99", inputs.C4.with_(n_r=45, n_theta=12, rstar_min=60.0, rstar_max=150.0, words=4)),
     ("qd-m0-a0.3", inputs.C1.with_(n_r=37, n_theta=8, rstar_min=70.0, rstar_max=140.0, m=0, a_over_M=0.3, words=4)),
+    # the other spin weights and negative m (every |s| <= 2 and any m are valid)
+    ("fp64-s-1-m-1", inputs.C1.with_(n_r=45, n_theta=12, rstar_min=70.0, rstar_max=140.0, s=-1, m=-1,
+                                     a_over_M=0.7, words=1)),
+    ("fp64-s2-m-2", inputs.C1.with_(n_r=41, n_theta=16, rstar_min=70.0, rstar_max=140.0, s=2, m=-2,
+                                    a_over_M=0.9, words=1)),
+    ("dd-s1-m-2", inputs.C1.with_(n_r=45, n_theta=12, rstar_min=70.0, rstar_max=140.0, s=1, m=-2,
+                                  a_over_M=0.95, words=2)),
+    ("dd-s-1-m3", inputs.C1.with_(n_r=39, n_theta=10, rstar_min=70.0, rstar_max=140.0, s=-1, m=3,
+                                  a_over_M=0.4, words=2)),
+    ("qd-s2-m-3", inputs.C1.with_(n_r=41, n_theta=12, rstar_min=70.0, rstar_max=140.0, s=2, m=-3,
+                                  a_over_M=0.5, words=4)),
+    ("qd-s1-m-1", inputs.C1.with_(n_r=37, n_theta=8, rstar_min=70.0, rstar_max=140.0, s=1, m=-1,
+                                  a_over_M=0.99, words=4)),
 ]
 
 
@@ -408,7 +421,13 @@ def test_checkpoint_restart_and_graph_are_bitwise():
     for f in range(4):
         assert np.array_equal(h.read_field(f), full[f])
     h.set_initial(*fields)
-    h.use_graph(3)                # an odd graph length is rounded to an even launch count
+    h.use_graph(3)                # an odd launch count: replays alternate between the two graphs
+    h.step(10)
+    assert h.graph_replays == 3 + 3
+    for f in range(4):
+        assert np.array_equal(h.read_field(f), full[f])
+    h.set_initial(*fields)
+    h.prepare_graph()             # both graphs captured up front; results unchanged
     h.step(10)
     for f in range(4):
         assert np.array_equal(h.read_field(f), full[f])
@@ -444,3 +463,113 @@ def test_device_arithmetic_matches_host(words):
     b = rng.standard_normal((257, words)) * np.array([1, 2 ** -60, 2 ** -120, 2 ** -180][:words])
     for op in (0, 1, 2, 3, 4):
         assert np.array_equal(T.arith(words, op, a, b, device=True), T.arith(words, op, a, b)), op
+
+
+def _mp_words(x, W):
+    """Nearest W-word non-overlapping float64 expansion of an mp number."""
+    out = []
+    for _ in range(W):
+        v = float(x)
+        out.append(v)
+        x = x - mp.mpf(v)
+    return out
+
+
+def _oracle_planes(w, tab):
+    """The eight scaled coefficient planes of teuk_set_coefficients (half
+    nodes, nodes), rounded to the workload's words from the oracle's tables."""
+    W = w.words
+    out = {}
+    with mp.workprec(450):
+        scal = {0: (tab["dt"] / 2, tab["dt"] / 2 / tab["h"]), 1: (tab["dt"], tab["dt"] / tab["h"])}
+        for which, key in ((0, "half"), (1, "full")):
+            s_, si = scal[which]
+            nr = len(tab[key][0])
+            a = np.empty((8, w.n_theta, nr, W))
+            for j in range(w.n_theta):
+                for i in range(nr):
+                    b, Wc, K, Ct, C0 = tab[key][j][i]
+                    vals = [si * b, s_ * Wc, si * K.real, si * K.imag, s_ * Ct.real, s_ * Ct.imag,
+                            s_ * C0.real, s_ * C0.imag]
+                    for c in range(8):
+                        a[c, j, i] = _mp_words(vals[c], W)
+            out[which] = a
+    return out
+
+
+@pytest.mark.parametrize("words,fuse", [(1, 4), (1, 1), (2, 1), (2, 2)])
+def test_stepping_on_injected_oracle_coefficients(words, fuse):
+    """The oracle's 450-bit coefficients, rounded to the working words and
+    injected through teuk_set_coefficients, drive the step (for FP64 this is
+    the stored-plane kernel, a separate instantiation from the per-point one),
+    and the result matches the oracle run on its own coefficients.  A handle
+    set to fused launches first: the switch to stored planes falls back to one
+    step per launch and the next step(1) runs (and is right)."""
+    w = inputs.C1.with_(n_r=47, n_theta=64, rstar_min=60.0, rstar_max=150.0, words=words, m=1, a_over_M=0.8)
+    fields = inputs.initial_fields(w)
+    _note("injected oracle coefficients words=%d fuse=%d" % (words, fuse))
+    tab = problem.build_tables(to_problem(w))
+    planes = _oracle_planes(w, tab)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), words)
+    h.set_sweep(T.SWEEP_WIDE2 if words == 1 else T.SWEEP_WIDE)
+    h.set_launch(16 if words == 1 else 4, 512)
+    h.set_fuse(fuse)
+    h.set_coefficients(0, planes[0])
+    h.set_coefficients(1, planes[1])
+    for which in (0, 1):
+        assert np.array_equal(h.coefficients(which), planes[which]), which
+    h.set_initial(*fields)
+    h.step(1)
+    h.step(10)
+    got = h.fields()
+    h.close()
+    err = rel_linf(got, oracle_run(w, fields, 11, tables=tab))
+    _note("  rel Linf = %.3e" % err)
+    assert err <= TOL[words]
+
+
+def test_nonfinite_initial_data_is_refused():
+    w = inputs.C1.with_(n_r=20, n_theta=8, rstar_min=60.0, rstar_max=150.0, words=2)
+    fields = [np.array(f) for f in inputs.initial_fields(w)]
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), 2)
+    h.set_initial(*fields)
+    h.step(2)
+    before = h.fields()
+    for bad in (np.nan, np.inf, -np.inf):
+        f = [x.copy() for x in fields]
+        f[3][4, 7, 1] = bad
+        with pytest.raises(T.TeukError) as ex:
+            h.set_initial(*f)
+        assert ex.value.code == T.TEUK_ENONFINITE
+    after = h.fields()                       # nothing was uploaded
+    for c in range(4):
+        assert np.array_equal(before[c], after[c])
+    f = [x.copy() for x in fields]
+    f[0][3, 0, 0] = np.nan                   # a radial boundary node is set to zero, not checked
+    h.set_initial(*f)
+    assert h.check_finite()
+    h.close()
+
+
+@pytest.mark.parametrize("words", [1, 2])
+def test_host_round_trip_is_bitwise(words):
+    """The host round-trip measurement mode (state to host memory and back
+    after every step) gives the same bits as resident stepping."""
+    w = inputs.C1.with_(n_r=47, n_theta=32, rstar_min=60.0, rstar_max=150.0, words=words, m=2, a_over_M=0.6)
+    fields = inputs.initial_fields(w)
+    ref = _run_gpu(w, fields, 7)
+    h = T.Teuk(w.s, w.m, w.a_over_M, _grid(w), words)
+    h.use_graph(4)
+    h.set_host_round_trip(True)
+    h.set_initial(*fields)
+    h.step(7)
+    assert h.graph_replays == 0
+    got = h.fields()
+    h.set_host_round_trip(False)
+    h.set_initial(*fields)
+    h.step(7)
+    again = h.fields()
+    h.close()
+    for c in range(4):
+        assert np.array_equal(got[c], ref[c]), c
+        assert np.array_equal(again[c], ref[c]), c

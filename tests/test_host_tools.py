@@ -94,3 +94,27 @@ def test_bench_counter_tables_follow_the_kernel_sources(monkeypatch):
     assert bench.measured("traffic", shape) is None
     for key in bench.MEASURED["fp64_flops_hw"]:
         assert len(key) == 5 and key[4] in (1, 2, 4)
+
+
+def test_graph_length_makes_the_timed_steps_graph_replays():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.graph_length(100, 20) == 20          # a short timed run is one replay
+    assert bench.graph_length(100, 10000) == 100
+    assert bench.graph_length(0, 20) == 0
+
+
+def test_issue_ceiling_from_the_instruction_mix(monkeypatch):
+    """All-FMA code can reach the whole FP64 peak; add-only code half of it."""
+    sys.path.insert(0, ROOT)
+    import bench
+    monkeypatch.setitem(bench.MEASURED, "source", bench.kernel_source_digest())
+    table = {("x", 1, 4, 256, 1): (80.0, 10.0, 10.0, 0.0), ("fma", 1, 4, 256, 1): (0.0, 0.0, 5.0, 0.0),
+             ("add", 1, 4, 256, 1): (7.0, 0.0, 0.0, 0.0)}
+    monkeypatch.setitem(bench.MEASURED, "fp64_mix", table)
+    r = bench.issue_ceiling("x", (1, 4, 256, 1), 30.0)
+    assert abs(r["issue_ceiling_frac"] - 110.0 / 200.0) < 1e-12
+    assert abs(r["frac_of_issue_ceiling"] - 0.30 / 0.55) < 1e-12
+    assert bench.issue_ceiling("fma", (1, 4, 256, 1), None)["issue_ceiling_frac"] == 1.0
+    assert bench.issue_ceiling("add", (1, 4, 256, 1), None)["issue_ceiling_frac"] == 0.5
+    assert bench.issue_ceiling("y", (1, 4, 256, 1), 10.0)["issue_ceiling_frac"] is None

@@ -142,3 +142,33 @@ def test_null_arguments_are_rejected():
     assert L.teuk_batch_set_fuse(None, 2) == T.TEUK_EINVAL
     assert L.teuk_destroy(None) == T.TEUK_OK
     assert L.teuk_arith_host(3, 0, None, None, None, 1) == T.TEUK_EINVAL
+
+
+@pytest.mark.parametrize("words", [1, 2, 4])
+def test_grid_size_limit_of_32_bit_plane_offsets(words):
+    """The step kernels address one word plane of the eight coefficient
+    components with 32-bit offsets: validation takes 8 * words * n_r * n_theta
+    up to 2^32 - 1 doubles and answers TEUK_ENOTSUP from 2^32 on, in every
+    precision, for FP64 too (its stored-plane mode after
+    teuk_set_coefficients uses the same offsets)."""
+    L = T.lib()
+    nth = 256
+    limit_points = (1 << 32) // (8 * words)          # first rejected point count
+    n_r_bad = limit_points // nth
+    assert n_r_bad * nth * 8 * words == 1 << 32
+    assert L.teuk_validate(-2, 2, 0.5, T.make_grid(n_r_bad, nth, -50, 250), words) == T.TEUK_ENOTSUP
+    assert "2^32" in L.teuk_last_error().decode()
+    assert L.teuk_validate(-2, 2, 0.5, T.make_grid(n_r_bad - 1, nth, -50, 250), words) == T.TEUK_OK
+    # a point count just below the limit that no n_theta of 256 reaches
+    assert L.teuk_validate(-2, 2, 0.5, T.make_grid(limit_points // 255 - 1, 255, -50, 250), words) == T.TEUK_OK
+    assert L.teuk_validate(-2, 2, 0.5, T.make_grid(limit_points // 200 + 1, 200, -50, 250), words) == T.TEUK_ENOTSUP
+
+
+def test_new_entry_points_reject_null_handles():
+    L = T.lib()
+    assert L.teuk_prepare_graph(None) == T.TEUK_EINVAL
+    assert L.teuk_batch_prepare_graph(None) == T.TEUK_EINVAL
+    assert L.teuk_graph_replays(None) == -1
+    assert L.teuk_set_host_round_trip(None, 1) == T.TEUK_EINVAL
+    assert L.teuk_set_observer(None, 0, None, None, 1, 1) == T.TEUK_EINVAL
+    assert L.teuk_read_observer(None, 0, None, None, None) == T.TEUK_EINVAL
