@@ -89,3 +89,43 @@ def worst_amplification(s: int, m: int, a_over_M: float, n_theta: int, h: float,
         if g > best:
             best, where = g, float(r)
     return best, where
+
+
+def radial_update_matrix(p, processes: int = 1) -> np.ndarray:
+    """The oracle's one-step map restricted to real, theta-independent data
+    (exact for s = 0, m = 0, a = 0, where such data stay theta-independent
+    and real): column q is one step of the fixed-point engine applied to the
+    q-th unit vector of (Phi, Pi) at the interior r* nodes, read back on the
+    first theta row and rounded to float64."""
+    from . import engine
+    if not (p.s == 0 and p.m == 0 and p.a_over_M == 0):
+        raise ValueError("theta-independent real data are invariant only for s = m = a = 0")
+    tab = problem.build_tables(p, processes=processes)
+    FT = engine.tables_to_fixed(tab)
+    nr, nth = p.n_r, p.n_theta
+    interior = list(range(1, nr - 1))
+    ni = len(interior)
+    U = np.zeros((2 * ni, 2 * ni))
+    one = 1 << engine.FRAC
+    plane = nr * nth
+    for col in range(2 * ni):
+        comp, i = (0, interior[col]) if col < ni else (2, interior[col - ni])
+        u = [0] * (4 * plane)
+        for j in range(nth):
+            u[comp * plane + j * nr + i] = one
+        out = engine.run_fixed(FT, nr, nth, u, 1)
+        for row in range(2 * ni):
+            c, k = (0, interior[row]) if row < ni else (2, interior[row - ni])
+            U[row, col] = out[c * plane + k] / one
+    return U
+
+
+def radial_spectral_radius(p, processes: int = 1):
+    """(largest |eigenvalue| of radial_update_matrix, r* node where its eigenvector peaks)."""
+    U = radial_update_matrix(p, processes=processes)
+    ev, vec = np.linalg.eig(U)
+    k = int(np.argmax(np.abs(ev)))
+    ni = U.shape[0] // 2
+    i = int(np.argmax(np.abs(vec[:ni, k]))) + 1
+    h = (p.rstar_max - p.rstar_min) / (p.n_r - 1)
+    return float(np.abs(ev[k])), p.rstar_min + i * h

@@ -14,7 +14,8 @@ struct CoefJob {
     double a_over_M, mass, rstar_min, rstar_max, cfl;
     double *ch, *cf, *wt;            // device outputs (planar, see kernels.hpp)
     int onfly;                       // FP64: write radial rows + theta factors instead of planes
-    double *rf, *rh, *trig;          // device outputs when onfly
+    int rows_mp;                     // dd: also write dd radial rows + theta factors (rf, rh, trig)
+    double *rf, *rh, *trig;          // device outputs when onfly or rows_mp
     double hdt[kMaxWords], dt[kMaxWords];   // scalars written by the pass (words of T)
     double dt_lead;
 };
@@ -23,6 +24,25 @@ struct CoefJob {
 hipError_t coef_pass_f64(CoefJob &job, hipStream_t stream);
 hipError_t coef_pass_dd(CoefJob &job, hipStream_t stream);
 hipError_t coef_pass_qd(CoefJob &job, hipStream_t stream);
+
+// Doubles of scratch the coefficient pass of one instance needs: r and Delta
+// at the n_r nodes and n_r - 1 half nodes, cos and sin^2 at the rows (all W
+// words each), and for FP64 the radial rows and theta factors when the pass
+// is to produce planes (coef_pass_into with planes_fp64).
+inline size_t coef_scratch_doubles(int words, int nr, int nth, bool planes_fp64) {
+    const size_t n = 2 * (size_t)nr - 1;
+    size_t d = (size_t)words * (2 * n + 2 * (size_t)nth);
+    if (planes_fp64) d += (size_t)kRadRow * n + 2 * (size_t)nth;
+    return d;
+}
+
+// The same pass with caller-owned scratch (coef_scratch_doubles doubles of
+// device memory): allocates nothing, does not synchronise.  planes_fp64
+// (FP64 only): produce the eight planes job.cf, job.ch (via radial rows kept
+// in scratch) instead of the rows.
+hipError_t coef_pass_into_f64(CoefJob &job, double *scratch, bool planes_fp64, hipStream_t stream);
+hipError_t coef_pass_into_dd(CoefJob &job, double *scratch, hipStream_t stream);
+hipError_t coef_pass_into_qd(CoefJob &job, double *scratch, hipStream_t stream);
 
 // FP64 test hook: the coefficient planes rebuilt from radial rows and theta factors.
 hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, const double *trig, double *cf,

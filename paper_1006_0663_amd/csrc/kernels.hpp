@@ -200,6 +200,100 @@ template <class T> __device__ __forceinline__ void gst(GLB double *p, uint32_t p
     for (int w = 0; w < words_of<T>::value; ++w) p[w * plane + idx] = mp_word(v, w);
 }
 
+// ------------------------------------------------------------------ multiword per-point coefficients
+// The radial row of kernels' per-point mode in working precision T: the same
+// sixteen factors as coef_fp64_radial_row (kVp2 .. kSIT8), each T, stored
+// [node][factor][word] (16 W doubles per node), computed from r and Delta
+// in T.  Products with a are taken in T; the other factors (2s, 4Mm, 6m, ...)
+// are small integers, exact in double.
+template <class T>
+MPA void coef_radial_row_mp(int s_, int m_, double M, double a_d, const T &r, const T &delta, const T &sg,
+                            const T &sgi, T *row) {
+    const double s = s_, m = m_;
+    const T a = mp_from<T>(a_d);
+    const T a2 = mp_mul(a, a), r2 = mp_mul(r, r), vp = mp_add(r2, a2);
+    const T rm = mp_sub(r, mp_from<T>(M));                    // r - M;  Delta' = 2 (r - M)
+    const T ddl = mp_pow2(rm, 2.0);
+    const T ir = mp_recip(r);
+    const T T1 = mp_mul_d(mp_msub(mp_from<T>(M), mp_sub(r2, a2), mp_mul(r, delta)), 2.0 * s);
+    const T T2 = mp_mul(mp_mul_d(r, 4.0 * M * m), a);
+    const T T3 = mp_mul(mp_mul_d(delta, 2.0 * s), a);
+    const T T4 = mp_mul(mp_mul(delta, ir), mp_add(mp_mul_d(ddl, 3.0 * (s + 1.0)), mp_mul_d(mp_mul(delta, ir), 6.0)));
+    const T T5 = mp_mul(mp_add(mp_mul_d(mp_mul(delta, ir), 6.0 * m), mp_mul_d(rm, 4.0 * m * s)), a);
+    const T T6 = mp_madd(delta, mp_madd(mp_mul_d(vp, 6.0), ir, mp_pow2(r, 2.0)), mp_mul_d(mp_mul(vp, ddl), s));
+    const T T7 = mp_mul(mp_mul_d(vp, 2.0 * m), a);
+    const T T8 = mp_pow2(mp_mul(mp_mul(a2, delta), mp_msub(mp_pow2(r, 4.0), delta, mp_mul(vp, ddl))), 0.5);
+    row[kVp2] = mp_mul(vp, vp);
+    row[kA2D] = mp_mul(a2, delta);
+    row[kVp] = vp;
+    row[kSD] = mp_mul(sg, delta);
+    row[kSIVp] = mp_mul(sgi, vp);
+    row[kST1] = mp_mul(sg, T1);
+    row[kST2] = mp_mul(sg, T2);
+    row[kST3] = mp_mul(sg, T3);
+    row[kST4] = mp_mul(sg, T4);
+    row[kST5] = mp_mul(sg, T5);
+    row[kSIT1] = mp_mul(sgi, T1);
+    row[kSIT2] = mp_mul(sgi, T2);
+    row[kSIT3] = mp_mul(sgi, T3);
+    row[kSIT6] = mp_mul(sgi, T6);
+    row[kSIT7] = mp_mul(sgi, T7);
+    row[kSIT8] = mp_mul(sgi, T8);
+}
+
+struct MpRowParams {
+    int n_full, n_half, s, m;
+    double mass, a;
+};
+
+// rows of every node (t < n_full) and half node; r and Delta planar [word][t]
+template <class T>
+__global__ void coef_mp_rows_kernel(MpRowParams P, T s_half, T si_half, T s_full, T si_full, const double *r_in,
+                                    const double *delta_in, double *rf, double *rh) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = P.n_full + P.n_half;
+    if (t >= n) return;
+    constexpr int W = words_of<T>::value;
+    const bool half = t >= P.n_full;
+    T row[kRadRow];
+    coef_radial_row_mp<T>(P.s, P.m, P.mass, P.a, ld<T>(r_in, (size_t)n, (size_t)t), ld<T>(delta_in, (size_t)n, (size_t)t),
+                          half ? s_half : s_full, half ? si_half : si_full, row);
+    double *out = half ? rh + (size_t)(t - P.n_full) * kRadRow * W : rf + (size_t)t * kRadRow * W;
+    for (int k = 0; k < kRadRow; ++k)
+        for (int w = 0; w < W; ++w) out[k * W + w] = mp_word(row[k], w);
+}
+
+// 1/sqrt(x) in double-double: the FP64 value (about one ulp) refined by one
+// Newton step y + y (1 - x y^2) / 2 evaluated in double-double, which
+// squares its relative error.
+MPA dd rsqrt_dd(const dd &x) {
+    const double y0 = rsqrt_nr(x.x0);
+    dd y2;
+    two_prod(y0, y0, y2.x0, y2.x1);                            // y0^2 exactly
+    const dd e = mp_msub(x, y2, mp_from<dd>(1.0));             // 1 - x y0^2
+    return mp_add(mp_from<dd>(y0), mp_mul_d(e, 0.5 * y0));
+}
+
+// The eight scaled coefficients of a point from its double-double radial row
+// (16 dd factors at row, [factor][word]) and cos, sin^2 of its theta row:
+// the terms of coef_fp64_point in double-double.
+template <class RowPtr>
+MPA void coef_dd_point(RowPtr row, const dd &cs, const dd &s2, dd *c) {
+    auto f = [&](int k) { return dd{row[2 * k], row[2 * k + 1]}; };
+    const dd X = mp_msub(f(kA2D), s2, f(kVp2));
+    const dd rq = rsqrt_dd(X);
+    const dd q = mp_mul(rq, rq);
+    const dd b = mp_mul(f(kVp), rq);
+    c[0] = mp_mul(f(kSIVp), rq);
+    c[1] = mp_mul(f(kSD), q);
+    c[2] = mp_mul(q, mp_sub(mp_mul(mp_mul(s2, q), f(kSIT8)), mp_madd(b, f(kSIT1), f(kSIT6))));
+    c[3] = mp_neg(mp_mul(q, mp_madd(b, mp_madd(cs, f(kSIT3), f(kSIT2)), f(kSIT7))));
+    c[4] = mp_mul(q, f(kST1));
+    c[5] = mp_mul(q, mp_madd(cs, f(kST3), f(kST2)));
+    c[6] = mp_mul(q, f(kST4));
+    c[7] = mp_mul(q, f(kST5));
+}
+
 // ------------------------------------------------------------------ coefficient pass
 struct RadialParams {
     int n_full, n_half;
@@ -876,7 +970,14 @@ __device__ __forceinline__ cx<T> stencil_ghosted(const d2 *slot, int rs, int j, 
 // CM: coefficient mode -- 0 stored planes, 1 (FP64) per point from radial
 // rows staged in LDS, 2 (FP64, n_theta a multiple of the wavefront size, so
 // a wavefront lies in one group and its column is uniform) per point from
-// radial rows read with scalar loads.
+// radial rows read with scalar loads, 3 (multiword) stored planes requested
+// one phase ahead: the planes of the next iteration's two stages are loaded
+// right after this iteration's stage 1, so their memory latency overlaps
+// the half-step stencil, the next puts and the first barrier instead of
+// following a barrier.  Same values, same arithmetic: bitwise equal to 0.
+// 4 (double-double) per point from double-double radial rows (the FP64
+// mode's factors, coef_dd_point): no coefficient planes are read; the
+// coefficients differ from the stored planes by rounding only.
 // Launch arguments of a one-instance launch, passed by value so that the
 // state loads need no descriptor load first (they arrive with the kernel
 // arguments, preloaded into SGPRs where the hardware supports it).
@@ -959,11 +1060,30 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         cs_j = gptr(I.trig)[jj];
         s2_j = gptr(I.trig)[nth + jj];
     }
+    T cs_m = mp_from<T>(0.0), s2_m = mp_from<T>(0.0);    // multiword per-point mode: cos, sin^2 of row j
+    if constexpr (W == 2 && CM == 4) {
+        cs_m = gld<T>(gptr(I.trig), (uint32_t)nth, (uint32_t)jj);
+        s2_m = gld<T>(gptr(I.trig) + W * nth, (uint32_t)nth, (uint32_t)jj);
+    }
     // one stage at node (half = false) or half node i, row j, with the
     // coefficients of that point
+    // CM == 3: the planes of one stage's P points, loaded ahead of use
+    auto load_planes = [&](bool half, int i, T *cf) {
+        const GLB double *pl = gptr(half ? I.ch : I.cf);
+        const uint32_t pn = half ? hplane : plane;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cf[q] = gld<T>(pl + q * W * pn, pn, (uint32_t)(i * nth + jj));
+    };
+    T pre2[CM == 3 ? P : 1][8], pre1[CM == 3 ? P : 1][8];
     auto stage = [&](bool half, int i, const Pt<T> &base, const Pt<T> &bar, const Pt<T> &d, const cx<T> &lbar,
-                     const T &s) -> Pt<T> {
-        if constexpr (W == 1 && CM == 2) {
+                     const T &s, const T *pre) -> Pt<T> {
+        if constexpr (CM == 3) {
+            return lw_stage(base, bar, d, lbar, pre, s);
+        } else if constexpr (W == 2 && CM == 4) {
+            T c[8];
+            coef_dd_point(gptr(half ? I.rh : I.rf) + (uint32_t)(i * kRadRow * W), cs_m, s2_m, c);
+            return lw_stage(base, bar, d, lbar, c, s);
+        } else if constexpr (W == 1 && CM == 2) {
             const int iu = __builtin_amdgcn_readfirstlane(i);
             return lw_stage_row(base, bar, d, lbar, (const CNS double *)(half ? I.rh : I.rf) + iu * kRadRow, cs_j,
                                 s2_j, s);
@@ -1022,6 +1142,15 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         // FP64 stages run on every lane with clamped indices (results of idle
         // lanes and of columns outside the segment are discarded); only the
         // stores are conditional, which keeps each phase one basic block.
+        if constexpr (CM == 3) {
+            if (t == 0) {
+                // first iteration of a step: this iteration's stage-1 planes
+                // (it has no stage 2)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    load_planes(true, min(max((NS == 1 ? a : as) + k0 + p - 1, a), e - 1), pre1[p]);
+            }
+        }
         if (t >= 1) {
             // stage 2 (lw2) at node a + kp - 1 for the columns kp of the previous run
             const int k0p = k0 - G * P;
@@ -1040,7 +1169,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                     const int ic = min(max(i, a), e);
                     const Pt<T> &ua = p == 0 ? uh_m : uh_l[p > 0 ? p - 1 : 0];
                     const cx<T> &la = p == 0 ? lh_m : lh_l[p > 0 ? p - 1 : 0];
-                    un = stage(false, ic, u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), dt);
+                    un = stage(false, ic, u_l[p], pt_avg(ua, uh_l[p]), pt_diff(ua, uh_l[p]), c_avg(la, lh_l[p]), dt,
+                               pre2[CM == 3 ? p : 0]);
                 }
                 if constexpr (NS == 1) {
                     if (on) gst_pt(uout, plane, (uint32_t)(i * nth + j), un);
@@ -1075,10 +1205,20 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
                 const Pt<T> &ua = p == 0 ? u_m1 : u_c[p > 0 ? p - 1 : 0];
                 const cx<T> &la = p == 0 ? l_m1 : l_c[p > 0 ? p - 1 : 0];
                 const Pt<T> bar = pt_avg(ua, u_c[p]);
-                uh[p] = stage(true, hc, bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), hdt);
+                uh[p] = stage(true, hc, bar, bar, pt_diff(ua, u_c[p]), c_avg(la, l_c[p]), hdt, pre1[CM == 3 ? p : 0]);
                 if (on) xput_ghosted<T>(xh + p * CH * RS, RS, j, nth, uh[p].phi);
             }
             if (last_on && k0 + P - 1 >= 1) xput<T>(XHI + sn, nth, j, uh[P - 1].pi);
+        }
+        if constexpr (CM == 3) {
+            // the next iteration's planes: its stage 2 takes this run's
+            // columns, its stage 1 the next run's
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int base = (NS == 1 ? a : as) - 1;
+                load_planes(false, min(max(base + k0 + p, a), e), pre2[p]);
+                load_planes(true, min(max(base + k0 + G * P + p, a), e - 1), pre1[p]);
+            }
         }
         __syncthreads();                                                        // B3
         cx<T> lh[P];

@@ -3,6 +3,9 @@
 
 namespace lwk {
 hipError_t coef_pass_dd(CoefJob &job, hipStream_t stream) { return coef_pass<dd>(job, stream); }
+hipError_t coef_pass_into_dd(CoefJob &job, double *scratch, hipStream_t stream) {
+    return coef_pass_into<dd>(job, scratch, false, stream);
+}
 hipError_t step_dd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
     return step_launch<dd>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);

@@ -3,6 +3,9 @@
 
 namespace lwk {
 hipError_t coef_pass_f64(CoefJob &job, hipStream_t stream) { return coef_pass<double>(job, stream); }
+hipError_t coef_pass_into_f64(CoefJob &job, double *scratch, bool planes_fp64, hipStream_t stream) {
+    return coef_pass_into<double>(job, scratch, planes_fp64, stream);
+}
 hipError_t step_f64(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
     return step_launch<double>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);

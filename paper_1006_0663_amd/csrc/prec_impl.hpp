@@ -83,15 +83,18 @@ template <class T> CoefSetup<T> coef_setup(CoefJob &J) {
     return S;
 }
 
+// The coefficient pass of one instance on `stream`, with its intermediate
+// tables in `scratch` (coef_scratch_doubles of them, caller-owned device
+// memory); allocates nothing and does not synchronise.  FP64 with J.onfly
+// writes the radial rows and theta factors (J.rf, J.rh, J.trig); with
+// planes_fp64 it writes them to scratch and expands them to the eight
+// planes J.cf, J.ch with the per-point routine the step kernel uses;
+// otherwise (and for dd, qd) the planes come from coef_point_kernel.
 template <class T>
-hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
+hipError_t coef_pass_into(CoefJob &J, double *scratch, bool planes_fp64, hipStream_t stream) {
     constexpr int W = words_of<T>::value;
     const int nth = J.nth, n = 2 * J.nr - 1;
     CoefSetup<T> S = coef_setup<T>(J);
-    double *scratch = nullptr;
-    const size_t nscr = (size_t)W * (2 * (size_t)n + 2 * (size_t)nth);
-    hipError_t err = hipMalloc((void **)&scratch, nscr * sizeof(double));
-    if (err != hipSuccess) return err;
     double *r_out = scratch, *d_out = scratch + (size_t)W * n;
     double *cos_out = d_out + (size_t)W * n, *sin2_out = cos_out + (size_t)W * nth;
     coef_radial_kernel<T><<<(n + 127) / 128, 128, 0, stream>>>(S.RP, S.rsmin, S.h, S.rp, S.dpm, S.A, S.B,
@@ -99,22 +102,53 @@ hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
     coef_theta_kernel<T><<<(nth + 63) / 64, 64, 0, stream>>>(S.TP, S.dth, cos_out, sin2_out, J.wt);
     bool rows = false;
     hipError_t ecopy = hipSuccess;
-    if constexpr (W == 1) rows = J.onfly != 0;
+    if constexpr (W == 1) rows = J.onfly != 0 || planes_fp64;
     if (rows) {
+        double *rf = J.rf, *rh = J.rh, *trig = J.trig;
+        if (planes_fp64) {
+            rf = sin2_out + (size_t)W * nth;
+            rh = rf + (size_t)kRadRow * J.nr;
+            trig = rh + (size_t)kRadRow * (J.nr - 1);
+        }
         const double sh = mp_lead(S.hdt), sih = mp_lead(mp_mul(S.hdt, S.ih));
         const double sf = mp_lead(S.dt), sif = mp_lead(mp_mul(S.dt, S.ih));
         Fp64RowParams FP{J.nr, J.nr - 1, J.s, J.m, S.PP.mass, S.PP.a, sh, sih, sf, sif};
-        coef_fp64_rows_kernel<<<(n + 127) / 128, 128, 0, stream>>>(FP, r_out, d_out, J.rf, J.rh);
-        ecopy = hipMemcpyAsync(J.trig, cos_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
+        coef_fp64_rows_kernel<<<(n + 127) / 128, 128, 0, stream>>>(FP, r_out, d_out, rf, rh);
+        ecopy = hipMemcpyAsync(trig, cos_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
         if (ecopy == hipSuccess)
-            ecopy = hipMemcpyAsync(J.trig + nth, sin2_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
+            ecopy = hipMemcpyAsync(trig + nth, sin2_out, sizeof(double) * nth, hipMemcpyDeviceToDevice, stream);
+        if (planes_fp64 && ecopy == hipSuccess) {
+            dim3 grid((nth + 63) / 64, n);
+            coef_fp64_planes_kernel<<<grid, 64, 0, stream>>>(J.nr, nth, rf, rh, trig, J.cf, J.ch);
+        }
     } else {
         dim3 grid((nth + 63) / 64, n);
         coef_point_kernel<T><<<grid, 64, 0, stream>>>(S.PP, r_out, d_out, cos_out, sin2_out, S.hdt,
                                                        mp_mul(S.hdt, S.ih), S.dt, mp_mul(S.dt, S.ih), J.ch, J.cf);
+        if constexpr (W == 2) if (J.rows_mp) {
+            // multiword radial rows [node][factor][word] and theta factors
+            // [cos, sin^2][word][row] for the per-point coefficient mode
+            MpRowParams MP{J.nr, J.nr - 1, J.s, J.m, S.PP.mass, S.PP.a};
+            coef_mp_rows_kernel<T><<<(n + 127) / 128, 128, 0, stream>>>(MP, S.hdt, mp_mul(S.hdt, S.ih), S.dt,
+                                                                         mp_mul(S.dt, S.ih), r_out, d_out, J.rf,
+                                                                         J.rh);
+            ecopy = hipMemcpyAsync(J.trig, cos_out, sizeof(double) * 2 * (size_t)W * nth, hipMemcpyDeviceToDevice,
+                                   stream);
+        }
     }
-    err = hipGetLastError();
+    hipError_t err = hipGetLastError();
     if (err == hipSuccess) err = ecopy;
+    return err;
+}
+
+// The coefficient pass of teuk_create: scratch from hipMalloc, synchronous.
+template <class T>
+hipError_t coef_pass(CoefJob &J, hipStream_t stream) {
+    constexpr int W = words_of<T>::value;
+    double *scratch = nullptr;
+    hipError_t err = hipMalloc((void **)&scratch, coef_scratch_doubles(W, J.nr, J.nth, false) * sizeof(double));
+    if (err != hipSuccess) return err;
+    err = coef_pass_into<T>(J, scratch, false, stream);
     hipError_t e2 = hipStreamSynchronize(stream);
     if (err == hipSuccess) err = e2;
     e2 = hipFree(scratch);
@@ -286,8 +320,18 @@ hipError_t wide_launch(int nt, int run, int cmode, int tm, int ns, size_t lds, c
 #undef LWK_WIDE
         return hipErrorInvalidValue;
     } else {
-        if (run != 1 || cmode != 0) return hipErrorInvalidValue;
-        return wide_launch_o<T, 1, 0>(nt, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+        if (run != 1) return hipErrorInvalidValue;
+        if (cmode == 0)
+            return wide_launch_o<T, 1, 0>(nt, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+        // planes requested one phase ahead: double-double only (quad-double
+        // has no registers to spare for a second set of planes)
+        if constexpr (words_of<T>::value == 2) {
+            if (cmode == 3)
+                return wide_launch_o<T, 1, 3>(nt, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+            if (cmode == 4)
+                return wide_launch_o<T, 1, 4>(nt, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
+        }
+        return hipErrorInvalidValue;
     }
 }
 

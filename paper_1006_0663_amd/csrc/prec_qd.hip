@@ -3,6 +3,9 @@
 
 namespace lwk {
 hipError_t coef_pass_qd(CoefJob &job, hipStream_t stream) { return coef_pass<qd>(job, stream); }
+hipError_t coef_pass_into_qd(CoefJob &job, double *scratch, hipStream_t stream) {
+    return coef_pass_into<qd>(job, scratch, false, stream);
+}
 hipError_t step_qd(int nt, int seg, bool onfly, size_t lds, const InstDev *insts, const WorkItem *items, int nitems, int parity,
                    hipStream_t stream) {
     return step_launch<qd>(nt, seg, onfly, lds, insts, items, nitems, parity, stream);

@@ -25,6 +25,9 @@ constexpr unsigned long long kMaxPlaneDoubles = 1ull << 32;
 constexpr int kMaxObserverPoints = 1024;
 constexpr double kMaxObserverDoubles = 268435456.0;   // 2^28 doubles (2 GiB) of records
 
+
+
+
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
@@ -34,6 +37,7 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(e == hipErrorOutOfMemory ? TEUK_ENOMEM : TEUK_EDEVICE,
                 std::string(what) + ": " + hipGetErrorString(e));
 }
+
 
 int validate(int s, int m, double a_over_M, const teuk_grid *g, int prec) {
     (void)m;
@@ -64,6 +68,16 @@ int validate(int s, int m, double a_over_M, const teuk_grid *g, int prec) {
     return TEUK_OK;
 }
 
+// Coefficient source of the double-double wide sweep (lwk::wide_launch
+// cmode): 0 stored planes loaded in the stage, 3 the same planes requested
+// one phase ahead (bitwise equal to 0), 4 rebuilt per point from
+// double-double radial rows.  TEUK_DD_COEF=0|3|4 overrides the default.
+int dd_cmode_default() {
+    const char *v = std::getenv("TEUK_DD_COEF");
+    if (v && (v[0] == '0' || v[0] == '3' || v[0] == '4') && v[1] == 0) return v[0] - '0';
+    return 0;
+}
+
 struct Instance {
     int s = 0, m = 0, words = 1, reach = 5;
     double a_over_M = 0.0;
@@ -71,6 +85,7 @@ struct Instance {
     double *u[2] = {nullptr, nullptr};
     double *ch = nullptr, *cf = nullptr, *wt = nullptr;
     int onfly = 0;                                   // FP64: per-point coefficients from rows
+    int injected = 0;                                // coefficients set by teuk_set_coefficients: planes only
     double *rf = nullptr, *rh = nullptr, *trig = nullptr;
     double hdt[lwk::kMaxWords] = {}, dt[lwk::kMaxWords] = {};
     double dt_lead = 0.0;
@@ -93,6 +108,7 @@ struct Batch {
     int tm = 0;              // wide sweep: unrolled iteration count (0 = loop)
     int fuse = 1;            // time steps per launch (wide sweep)
     bool no_scalar_rows = std::getenv("TEUK_NO_SCALAR_ROWS") != nullptr;   // diagnostics: force LDS rows
+    int dd_cmode = dd_cmode_default();         // dd wide sweep: coefficient source (see dd_cmode_default)
     size_t lds = 0;          // dynamic LDS bytes per block of the step kernel
     lwk::InstDev *d_inst = nullptr;
     lwk::WorkItem *d_items = nullptr;
@@ -195,7 +211,7 @@ hipError_t step_launch(const Batch &b, int parity, int ns) {
                 return lwk::wide_f64(b.nt, run, b.cmode, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
                                      b.stream, false);
             case 2:
-                return lwk::wide_dd(b.nt, run, 0, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
+                return lwk::wide_dd(b.nt, run, b.cmode, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
                                     b.stream, false);
             default:
                 return lwk::wide_qd(b.nt, run, 0, b.tm, ns, b.lds, onep, b.d_inst, b.d_items, b.nitems, parity,
@@ -283,6 +299,7 @@ int build_worklist(Batch &h) {
     b.sweep_req = h.sweep_req;
     b.fuse = h.fuse;
     b.no_scalar_rows = h.no_scalar_rows;
+    b.dd_cmode = h.dd_cmode;
     int maxnth = 0;
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     b.sweep = b.sweep_req >= 0 ? b.sweep_req : default_sweep(b.words);
@@ -296,7 +313,11 @@ int build_worklist(Batch &h) {
             onfly = onfly && I.onfly;
             wave_cols = wave_cols && I.g.n_theta % 64 == 0;
         }
-        b.cmode = !onfly ? 0 : (wave_cols && !b.no_scalar_rows ? 2 : 1);
+        bool injected = false;
+        for (auto &I : b.inst) injected = injected || I.injected;
+        // (injected coefficients exist only as planes: no per-point rebuild)
+        const int dd_mode = (b.dd_cmode == 4 && injected) ? 0 : b.dd_cmode;
+        b.cmode = !onfly ? (b.words == 2 ? dd_mode : 0) : (wave_cols && !b.no_scalar_rows ? 2 : 1);
         // FP64 radial rows of a segment stay within kMaxRowsLds
         while (b.segcols > 1 && lwk::wide_rows_bytes(b.segcols + 2 * b.fuse) > kMaxRowsLds) b.segcols -= 1;
         const size_t lim = (size_t)device_lds_limit();
@@ -360,7 +381,7 @@ int build_worklist(Batch &h) {
                     if (e != hipSuccess) break;
                     e = b.words == 1
                             ? lwk::wide_f64(b.nt, run, b.cmode, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
-                        : b.words == 2 ? lwk::wide_dd(b.nt, run, 0, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
+                        : b.words == 2 ? lwk::wide_dd(b.nt, run, b.cmode, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true)
                                        : lwk::wide_qd(b.nt, run, 0, b.tm, ns, b.lds, o, nullptr, nullptr, 0, 0, nullptr, true);
                 }
             }
@@ -477,6 +498,7 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
         const size_t ch_bytes = 8 * (size_t)W * I.hplane() * sizeof(double);
         const size_t wt_bytes = (size_t)(2 * I.reach + 1) * W * g[k].n_theta * sizeof(double);
         I.onfly = (W == 1);
+        const bool rows_mp = (W == 2);               // double-double: radial rows for the per-point mode
         if ((e = hipMalloc((void **)&I.u[0], st_bytes)) != hipSuccess ||
             (e = hipMalloc((void **)&I.u[1], st_bytes)) != hipSuccess ||
             (e = hipMalloc((void **)&I.wt, wt_bytes)) != hipSuccess)
@@ -490,6 +512,11 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
                    (e = hipMalloc((void **)&I.ch, ch_bytes)) != hipSuccess) {
             return hip_fail(e, "hipMalloc(coefficient planes)");
         }
+        if (rows_mp &&
+            ((e = hipMalloc((void **)&I.rf, (size_t)lwk::kRadRow * W * g[k].n_r * sizeof(double))) != hipSuccess ||
+             (e = hipMalloc((void **)&I.rh, (size_t)lwk::kRadRow * W * (g[k].n_r - 1) * sizeof(double))) != hipSuccess ||
+             (e = hipMalloc((void **)&I.trig, 2 * (size_t)W * g[k].n_theta * sizeof(double))) != hipSuccess))
+            return hip_fail(e, "hipMalloc(coefficient rows)");
         if ((e = hipMemsetAsync(I.u[0], 0, st_bytes, b.stream)) != hipSuccess ||
             (e = hipMemsetAsync(I.u[1], 0, st_bytes, b.stream)) != hipSuccess)
             return hip_fail(e, "hipMemset(state)");
@@ -508,6 +535,7 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
         J.cf = I.cf;
         J.wt = I.wt;
         J.onfly = I.onfly;
+        J.rows_mp = rows_mp;
         J.rf = I.rf;
         J.rh = I.rh;
         J.trig = I.trig;
@@ -1031,6 +1059,15 @@ int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
             I.cf = I.ch = nullptr;
             hipFree(cf);
             hipFree(ch);
+            return rc;
+        }
+    }
+    if (!I.injected) {
+        // the step must read the planes from now on (the per-point modes
+        // would ignore them)
+        I.injected = 1;
+        if (int rc = build_worklist(b)) {
+            I.injected = 0;
             return rc;
         }
     }

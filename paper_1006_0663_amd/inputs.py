@@ -95,12 +95,14 @@ BATCH_NTH = (32, 64, 128, 256)
 # l-projected compactly supported data: the late-time tail workloads.  a = 0
 # (Schwarzschild), where Price's law fixes the decay at a fixed radius to
 # t^-(2l+3); the grid keeps reflections from both Dirichlet ends away from the
-# observer (r* = 30) until t ~ 1,260 M.  dt = 0.3 dtheta (the s = 0, m = 0
-# angular operator has no pole term).
+# observer (r* = 30) until t ~ 1,260 M.  dt = 0.3 dtheta = 0.059 M (the s = 0,
+# m = 0 angular operator has no pole term) and dr* = 0.25 M: with dr* = 0.5 M
+# the radial discretisation has a growing mode near r ~ 2.7 M whenever
+# dt / dr* is below ~0.2 (the oracle's one-step map, oracle/stability.py).
 TAIL_RSTAR = (-600.0, 1000.0)
-S0_L0 = Workload("s0-l0-dd-3201x16", s=0, m=0, a_over_M=0.0, n_r=3201, n_theta=16, rstar_min=TAIL_RSTAR[0],
+S0_L0 = Workload("s0-l0-dd-6401x16", s=0, m=0, a_over_M=0.0, n_r=6401, n_theta=16, rstar_min=TAIL_RSTAR[0],
                  rstar_max=TAIL_RSTAR[1], words=2, steps=18000, cfl=0.3, profile="bump_legendre", ell=0)
-S0_L1 = S0_L0.with_(name="s0-l1-dd-3201x16", ell=1)
+S0_L1 = S0_L0.with_(name="s0-l1-dd-6401x16", ell=1)
 # rotating hole, s = 0, l = 2 data (spheroidal mode coupling): parity sizes
 S0_KERR = Workload("s0-l2-m1-a0.9", s=0, m=1, a_over_M=0.9, n_r=1024, n_theta=32, rstar_min=-200.0,
                    rstar_max=800.0, words=2, steps=2000, cfl=0.3, profile="bump_legendre", ell=2)

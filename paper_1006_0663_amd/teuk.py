@@ -173,13 +173,18 @@ class Teuk:
     def fields(self):
         return tuple(self.read_field(f) for f in range(4))
 
+    def _handle(self):
+        if not getattr(self, "h", None):
+            raise TeukError(TEUK_EINVAL, "handle is closed")
+        return self.h
+
     @property
     def dt(self):
-        return lib().teuk_dt(self.h)
+        return lib().teuk_dt(self._handle())
 
     @property
     def steps_done(self):
-        return lib().teuk_steps_done(self.h)
+        return lib().teuk_steps_done(self._handle())
 
     def set_step_index(self, n):
         _check(lib().teuk_set_step_index(self.h, int(n)))
@@ -349,3 +354,4 @@ def fp64_fma_probe(chains, blocks, threads, iters):
     if rc != TEUK_OK:
         raise TeukError(rc, "fp64 FMA probe failed")
     return tf.value, ms.value
+

@@ -51,6 +51,45 @@ extern "C" int coef_host(int words, int s, int m, double a_over_M, int nr, int n
     return rc;
 }
 
+// Double-double per-point mode: the planes the step kernel forms per point
+// from double-double radial rows (coef_radial_row_mp + coef_dd_point), same
+// layouts as coef_host.
+extern "C" int coef_host_dd_rows(int s, int m, double a_over_M, int nr, int nth, double rsmin, double rsmax,
+                                 double cfl, double mass, int order, double *ch, double *cf, double *wt, double *scal) {
+    CoefJob J{};
+    J.s = s; J.m = m; J.nr = nr; J.nth = nth; J.reach = order / 2;
+    J.a_over_M = a_over_M; J.mass = mass; J.rstar_min = rsmin; J.rstar_max = rsmax; J.cfl = cfl;
+    constexpr int W = 2;
+    const int n = 2 * J.nr - 1;
+    CoefSetup<dd> S = coef_setup<dd>(J);
+    std::vector<double> r((size_t)W * n), d((size_t)W * n), c((size_t)W * nth), s2((size_t)W * nth);
+    for (int t = 0; t < n; ++t) coef_radial_one<dd>(S.RP, t, S.rsmin, S.h, S.rp, S.dpm, S.A, S.B, r.data(), d.data());
+    for (int j = 0; j < nth; ++j) coef_theta_one<dd>(S.TP, j, S.dth, c.data(), s2.data(), wt);
+    std::vector<double> rows((size_t)kRadRow * W * n);
+    for (int t = 0; t < n; ++t) {
+        const bool half = t >= J.nr;
+        dd row[kRadRow];
+        coef_radial_row_mp<dd>(J.s, J.m, J.mass, J.a_over_M * J.mass, ld<dd>(r.data(), (size_t)n, (size_t)t),
+                               ld<dd>(d.data(), (size_t)n, (size_t)t), half ? S.hdt : S.dt,
+                               half ? mp_mul(S.hdt, S.ih) : mp_mul(S.dt, S.ih), row);
+        const int i = half ? t - J.nr : t, ni = half ? J.nr - 1 : J.nr;
+        for (int k = 0; k < kRadRow; ++k) {
+            rows[(size_t)t * kRadRow * W + 2 * k] = row[k].x0;
+            rows[(size_t)t * kRadRow * W + 2 * k + 1] = row[k].x1;
+        }
+        for (int j = 0; j < nth; ++j) {
+            dd cc[8];
+            coef_dd_point(rows.data() + (size_t)t * kRadRow * W, ld<dd>(c.data(), (size_t)nth, (size_t)j),
+                          ld<dd>(s2.data(), (size_t)nth, (size_t)j), cc);
+            double *out = half ? ch : cf;
+            const size_t plane = (size_t)ni * nth;
+            for (int k = 0; k < 8; ++k) st(out + (size_t)k * W * plane, plane, (size_t)i * nth + j, cc[k]);
+        }
+    }
+    for (int k = 0; k < kMaxWords; ++k) { scal[k] = J.hdt[k]; scal[kMaxWords + k] = J.dt[k]; }
+    return 0;
+}
+
 // One full step of the scheme on the host with the kernel's own stage routines
 // (lw_stage, pt_avg, pt_diff) and the device data layout; the angular operator
 // is applied with the same folded weights and reflected row index.

@@ -16,19 +16,27 @@ LIB = os.path.join(HERE, "host_emul", "libcoefhost.so")
 TOL = {1: 1e-14, 2: 1e-30, 4: 1e-62}
 
 
-def host_coefficients(w):
+def host_coefficients(w, dd_rows=False):
+    """The planes of the coefficient pass (dd_rows: of the double-double
+    per-point mode, built from double-double radial rows)."""
     L = ctypes.CDLL(LIB)
     D = ctypes.POINTER(ctypes.c_double)
     L.coef_host.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] + [ctypes.c_int] * 2 + [ctypes.c_double] * 4 + \
         [ctypes.c_int, D, D, D, D]
+    L.coef_host_dd_rows.argtypes = L.coef_host.argtypes[1:]
     W, nr, nth, R = w.words, w.n_r, w.n_theta, w.angular_order // 2
     ch = np.zeros((8, W, nr - 1, nth))
     cf = np.zeros((8, W, nr, nth))
     wt = np.zeros((2 * R + 1, W, nth))
     scal = np.zeros(8)
     p = lambda a: a.ctypes.data_as(D)
-    L.coef_host(W, w.s, w.m, w.a_over_M, nr, nth, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order,
-                p(ch), p(cf), p(wt), p(scal))
+    args = (w.s, w.m, w.a_over_M, nr, nth, w.rstar_min, w.rstar_max, w.cfl, w.mass, w.angular_order,
+            p(ch), p(cf), p(wt), p(scal))
+    if dd_rows:
+        assert W == 2
+        L.coef_host_dd_rows(*args)
+    else:
+        L.coef_host(W, *args)
     return ch, cf, wt, scal
 
 
@@ -36,11 +44,12 @@ def _val(words):
     return sum((mp.mpf(float(x)) for x in words), mp.mpf(0))
 
 
-@pytest.mark.parametrize("words", [1, 2, 4])
+@pytest.mark.parametrize("words,dd_rows", [(1, False), (2, False), (4, False), (2, True)],
+                         ids=["fp64", "dd", "qd", "dd-per-point"])
 @pytest.mark.parametrize("a,m", [(0.9, 3), (0.0, 2), (0.99, -1)])
-def test_host_coefficients_match_oracle(words, a, m):
+def test_host_coefficients_match_oracle(words, dd_rows, a, m):
     w = inputs.C2.with_(n_r=17, n_theta=8, words=words, a_over_M=a, m=m)
-    ch, cf, wt, scal = host_coefficients(w)
+    ch, cf, wt, scal = host_coefficients(w, dd_rows)
     tab = problem.build_tables(to_problem(w))
     with mp.workprec(450):
         assert abs(_val(scal[4:4 + words]) - tab["dt"]) <= TOL[words] * tab["dt"]

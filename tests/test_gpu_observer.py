@@ -117,9 +117,10 @@ def test_price_law_tail(w):
                                                                               w.rstar_min + i_obs * hr, j_obs))
     h.step(w.steps)
     steps, phi, total = h.read_observer()
+    dt = h.dt
     h.close()
     assert total == w.steps // every
-    t = steps * h.dt
+    t = steps * dt
     val = phi[:, 0, 0, :].sum(axis=1)                  # Re Phi (leading words suffice for a fit)
     assert np.all(phi[:, 0, 1, 0] == 0)                # a = 0 real data stay real
     sel = (t >= 400.0) & (t <= 1000.0)

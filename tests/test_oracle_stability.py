@@ -71,3 +71,28 @@ def test_long_runs_grow_at_cfl_half_and_not_at_0p15(name, s, m, a, nth, h, steps
     assert steps * math.log10(g5) > 100
     assert g15 ** steps < 200
     assert 2.0 < r5 < 3.2
+
+
+def _radial(h, dt):
+    from oracle import problem
+    n = int(round(60.0 / h)) + 1
+    k = math.pi / 5
+    return problem.Problem(s=0, m=0, a_over_M=0.0, n_r=n, n_theta=5, rstar_min=-20.0, rstar_max=40.0,
+                           cfl=dt / min(h, k))
+
+
+def test_tail_grid_is_radially_stable_and_a_coarser_one_is_not():
+    """The oracle's one-step map on theta-independent s = 0 data (exact: such
+    data stay theta-independent) around the hole, r* in [-20, 40]: with the
+    tail workloads' dt = 0.059 M and dr* = 0.25 M every mode is damped; with
+    dr* = 0.5 M (dt / dr* = 0.12) a mode near r ~ 2.7 M (r* ~ 0) grows by
+    0.65 % per step, which is what made a first choice of the tail grid blow
+    up.  At dt / dr* = 0.5 the coarse grid is stable again."""
+    g, where = S.radial_spectral_radius(_radial(0.25, 0.0589), processes=8)
+    print("dr* 0.25, dt 0.0589: spectral radius %.8f" % g)
+    assert g <= 1.0
+    g, where = S.radial_spectral_radius(_radial(0.5, 0.0589), processes=8)
+    print("dr* 0.5, dt 0.0589: spectral radius %.8f, mode at r* = %.1f" % (g, where))
+    assert g > 1.004 and -5.0 < where < 5.0
+    g, _ = S.radial_spectral_radius(_radial(0.5, 0.25), processes=8)
+    assert g <= 1.0
