@@ -252,6 +252,27 @@ int teuk_set_observer(teuk_t *h, int n_points, const int *i, const int *j, int e
  * observer. */
 int teuk_read_observer(teuk_t *h, long max_records, double *out, long *n_out, long *n_total);
 
+/* The coefficient pass into caller-owned device memory, allocating nothing:
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops with preallocated buffers, harnesses that forbid
+ * hipMalloc).  Same arguments and validation as teuk_create, and the same
+ * kernels as its coefficient pass, so the results equal teuk_get_coefficients
+ * of a handle created with the same arguments, bit for bit.  Outputs (device
+ * pointers, planar, theta row fastest; p = words):
+ *   d_ch[(c*p + w) * (n_r-1) * n_theta + i * n_theta + j]  half nodes, c = 0..7
+ *   d_cf[(c*p + w) * n_r * n_theta + i * n_theta + j]      nodes
+ *   d_wt[((k+R)*p + w) * n_theta + j]                       angular weights, R = order/2
+ * in the order and scaling of teuk_get_coefficients.  The intermediate tables
+ * (r and Delta at nodes and half nodes, cos and sin^2 per row, for FP64 also
+ * 16 radial factors per node) live in a device array of 2^20 doubles (8 MiB)
+ * that each GPU the library runs on holds until the process ends; a grid
+ * needing more (p (4 n_r + 2 n_theta - 2), plus 32 n_r + 2 n_theta - 16 for
+ * FP64) returns TEUK_EINVAL.  Nothing in it must start at zero.  Enqueued on
+ * `stream` (a hipStream_t, NULL = the null stream) on the current device,
+ * asynchronously; calls that overlap on one GPU share the array and race. */
+int teuk_coefficients_noalloc(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec,
+                              double *d_ch, double *d_cf, double *d_wt, void *stream);
+
 /* FP64 FMA throughput probe (the device's attainable FP64 vector rate, the
  * reference for the step kernels' FP64 operation rates): `blocks` x `threads`
  * lanes each run `chains` (1, 2, 4 or 8) independent FMA chains of `iters`

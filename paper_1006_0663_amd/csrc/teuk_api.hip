@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,7 +26,16 @@ constexpr unsigned long long kMaxPlaneDoubles = 1ull << 32;
 constexpr int kMaxObserverPoints = 1024;
 constexpr double kMaxObserverDoubles = 268435456.0;   // 2^28 doubles (2 GiB) of records
 
-
+// Scratch of teuk_coefficients_noalloc: a device array each GPU holds from
+// the library's load until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is handed to kernels and copies.
+constexpr size_t kScratchDoubles = (size_t)1 << 20;      // 8 MiB per device
+__device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
 
 
 int fail(int code, const std::string &msg) {
@@ -38,6 +48,22 @@ int hip_fail(hipError_t e, const char *what) {
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
+int scratch_on_current_device(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(TEUK_ENOTSUP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(TEUK_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TEUK_OK;
+}
 
 int validate(int s, int m, double a_over_M, const teuk_grid *g, int prec) {
     (void)m;
@@ -1247,6 +1273,42 @@ int teuk_read_observer(teuk_t *h, long max_records, double *out, long *n_out, lo
     }
     if (n_out) *n_out = n;
     if (n_total) *n_total = (long)c[1];
+    return TEUK_OK;
+}
+
+// ---- allocation-free coefficient pass (teuk_coefficients_noalloc)
+int teuk_coefficients_noalloc(int s, int m, double a_over_M, const teuk_grid *grid, teuk_precision prec,
+                              double *d_ch, double *d_cf, double *d_wt, void *stream) {
+    int rc = validate(s, m, a_over_M, grid, (int)prec);
+    if (rc != TEUK_OK) return rc;
+    if (!d_ch || !d_cf || !d_wt) return fail(TEUK_EINVAL, "output pointer is NULL");
+    const int W = (int)prec;
+    const size_t need = lwk::coef_scratch_doubles(W, grid->n_r, grid->n_theta, W == 1);
+    if (need > kScratchDoubles)
+        return fail(TEUK_EINVAL, "grid needs " + std::to_string(need) + " doubles of scratch; the library holds " +
+                                     std::to_string(kScratchDoubles));
+    double *scr = nullptr;
+    if ((rc = scratch_on_current_device(&scr)) != TEUK_OK) return rc;
+    lwk::CoefJob J{};
+    J.s = s;
+    J.m = m;
+    J.nr = grid->n_r;
+    J.nth = grid->n_theta;
+    J.reach = grid->angular_order / 2;
+    J.a_over_M = a_over_M;
+    J.mass = grid->mass;
+    J.rstar_min = grid->rstar_min;
+    J.rstar_max = grid->rstar_max;
+    J.cfl = grid->cfl;
+    J.ch = d_ch;
+    J.cf = d_cf;
+    J.wt = d_wt;
+    J.onfly = 0;
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e = W == 1 ? lwk::coef_pass_into_f64(J, scr, true, st)
+                 : W == 2 ? lwk::coef_pass_into_dd(J, scr, st)
+                          : lwk::coef_pass_into_qd(J, scr, st);
+    if (e != hipSuccess) return hip_fail(e, "coefficient pass");
     return TEUK_OK;
 }
 

@@ -84,6 +84,8 @@ _SIGS = {
                            ctypes.c_int, ctypes.c_long], ctypes.c_int),
     "teuk_read_observer": ([_P, ctypes.c_long, _D, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)],
                            ctypes.c_int),
+    "teuk_coefficients_noalloc": ([ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(Grid), ctypes.c_int,
+                                   _P, _P, _P, _P], ctypes.c_int),
     "teuk_fp64_fma_probe": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, _D, _D], ctypes.c_int),
     "teuk_arith_host": ([ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_int], ctypes.c_int),
     "teuk_arith_device": ([ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_int], ctypes.c_int),
@@ -355,3 +357,9 @@ def fp64_fma_probe(chains, blocks, threads, iters):
         raise TeukError(rc, "fp64 FMA probe failed")
     return tf.value, ms.value
 
+
+def coefficients_noalloc(s, m, a_over_M, grid: Grid, words, d_ch, d_cf, d_wt, stream=0):
+    """Coefficient pass into caller-owned device buffers (addresses as ints)
+    on `stream` (a hipStream_t as int); see teuk_coefficients_noalloc."""
+    _check(lib().teuk_coefficients_noalloc(s, m, a_over_M, ctypes.byref(grid), words, _P(d_ch), _P(d_cf),
+                                           _P(d_wt), _P(stream or 0)))
