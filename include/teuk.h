@@ -213,8 +213,9 @@ int teuk_batch_set_fuse(teuk_batch_t *b, int steps_per_launch);
  * shape, the stream or the observer drops the graphs. */
 int teuk_batch_use_graph(teuk_batch_t *b, int steps_per_graph);
 int teuk_use_graph(teuk_t *h, int steps_per_graph);
-/* Capture (and instantiate) both graphs now, so that no later teuk_step pays
- * for it; runs no steps.  No-op when graphs are off. */
+/* Capture, instantiate and upload both graphs now, so that no later
+ * teuk_step pays for it; runs no steps, returns after the upload.  No-op when
+ * graphs are off. */
 int teuk_prepare_graph(teuk_t *h);
 int teuk_batch_prepare_graph(teuk_batch_t *b);
 /* Graph replays launched since the handle was created. */

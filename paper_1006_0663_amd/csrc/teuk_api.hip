@@ -812,13 +812,20 @@ int prepare_graph(Batch &b) {
     if (int rc = check_ok(b)) return rc;
     if (b.graph_steps <= 0 || b.host_state) return TEUK_OK;
     for (int par = 0; par < 2; ++par) {
-        if (b.gexec[par]) continue;
-        const hipError_t e = capture_graph(b, par);
+        hipError_t e = b.gexec[par] ? hipSuccess : capture_graph(b, par);
+        // move the executable graph to the device now, so that its first
+        // replay does not pay for it
+        if (e == hipSuccess) e = hipGraphUpload(b.gexec[par], b.stream);
         if (e != hipSuccess) {
             b.sticky = TEUK_EDEVICE;
             drop_graph(b);
             return hip_fail(e, "graph capture");
         }
+    }
+    const hipError_t e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "graph upload");
     }
     return TEUK_OK;
 }

@@ -25,7 +25,15 @@ def main():
     ap.add_argument("--sweep", type=int, default=-1, help="0 segment, 1 wide, 2 wide with runs of two, -1 default")
     ap.add_argument("--fuse", type=int, default=1, help="steps per launch (1, 2 or 4)")
     ap.add_argument("--tuned", action="store_true", help="use the autotuner's shape (cached if tuned before)")
+    ap.add_argument("--time", type=int, default=0, metavar="REPS",
+                    help="also time REPS runs of --steps graph-replayed steps (HIP events) and print us/step")
+    ap.add_argument("--dd-coef", choices=("0", "3", "4"), default=None,
+                    help="double-double coefficient source (sets TEUK_DD_COEF): 0 stored planes, "
+                         "3 planes requested one phase ahead, 4 rebuilt per point")
     a = ap.parse_args()
+    if a.dd_coef is not None:
+        import os
+        os.environ["TEUK_DD_COEF"] = a.dd_coef          # read when the handle is created
     w = inputs.WORKLOADS[a.workload]
     torch.cuda.set_device(0)
     src = torch.empty(COPY_MIB << 20, dtype=torch.uint8, device="cuda")
@@ -46,10 +54,28 @@ def main():
         h.set_launch(a.segcols, a.block)
         h.set_fuse(a.fuse)
     h.step(a.steps)
+    timing = ""
+    if a.time:
+        stream = torch.cuda.Stream()
+        h.set_stream(stream.cuda_stream)
+        h.use_graph(min(100, a.steps))
+        h.prepare_graph()
+        with torch.cuda.stream(stream):
+            h.step(a.steps)                     # warm-up (clocks, caches)
+            ts = []
+            for _ in range(a.time):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                h.step(a.steps)
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e3 / a.steps)
+        timing = " us_per_step_min=%.3f all=%s" % (min(ts), ",".join("%.3f" % t for t in ts))
     ok = h.check_finite()
     h.close()
-    print("profile_step: %s %d steps sweep=%d segcols=%d block=%d fuse=%d finite=%s copy=%d MiB"
-          % (w.name, a.steps, a.sweep, a.segcols, a.block, a.fuse, ok, COPY_MIB), flush=True)
+    print("profile_step: %s %d steps sweep=%d segcols=%d block=%d fuse=%d finite=%s copy=%d MiB%s%s"
+          % (w.name, a.steps, a.sweep, a.segcols, a.block, a.fuse, ok, COPY_MIB,
+             "" if a.dd_coef is None else " dd_coef=" + a.dd_coef, timing), flush=True)
     return 0 if ok else 1
 
 
