@@ -23,51 +23,43 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 # Counter-derived figures, valid only for the launch shapes and kernel sources
-# they were taken with (`source` is kernel_source_digest() at that time;
-# otherwise they are reported as null); the summaries under profiles/ give the
-# commands (rocprofv3 --pmc on paper_1006_0663_amd/profile_step.py).
+# they were taken with (`source` is kernel_source_digest() of those sources;
+# for other sources they are reported as null).  profiles/lw_wide_fp64_4096x128.md
+# and profiles/lw_wide_valu_f64_counts.md give the rocprofv3 commands (--pmc on
+# paper_1006_0663_amd/profile_step.py, one MI355X).
 #  traffic: HBM bytes per launch of the headline kernel, FETCH_SIZE and
-#    WRITE_SIZE in KiB; FETCH_SIZE reads 131,093 KiB for a 256 MiB device copy
-#    (scale 2.0), WRITE_SIZE 262,144 KiB (scale 1.0).  Key: (sweep, segcols,
-#    block, steps per launch).
+#    WRITE_SIZE in KiB; a 256 MiB device copy reads FETCH_SIZE 131,093 KiB
+#    (scale 2.0) and WRITE_SIZE 262,144 KiB (scale 1.0).  Key: (sweep,
+#    segcols, block, steps per launch).
 #  fp64_flops_hw: FP64 operations per update as the hardware counts them
 #    (SQ_INSTS_VALU_FLOPS_FP64 = 2 FMA + ADD + MUL wave instructions, x 64
 #    lanes, per launch, over the updates of that launch): unlike the operation
 #    tally of opcount.py this includes the halo columns each segment
 #    recomputes and lanes whose results are discarded.  Key: (workload,
 #    sweep, segcols, block, steps per launch).
-# (The FP64 and double-double entries were taken with sources 11e2e15d9e62 —
-# those for runs of two with a95add959460 —, the quad-double entries with
-# 56fae8f58cd3; the device code of those sources
-# is instruction for instruction the code of the sources named below, whose
-# changes since were host-side or did not alter the generated kernels.)
+#  fp64_mix: FP64 VALU lane-instructions per update (ADD, MUL, FMA, TRANS),
+#    from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 in the same way.  Key as
+#    fp64_flops_hw.
 MEASURED = {
-    "source": "a95add959460", "fetch_scale": 2.0, "write_scale": 1.0,
-    # fp64_mix: FP64 VALU instructions per update (ADD, MUL, FMA, TRANS; wave
-    #   instructions x 64 lanes over the updates of a launch), from
-    #   SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64.  Key as fp64_flops_hw.
-    "fp64_mix": {},
-    "traffic": {(2, 16, 512, 4): (9886.8, 16384.0),
-                (2, 8, 256, 2): (9592.8, 16384.0), (2, 16, 512, 2): (9598.8, 16384.0),
-                (1, 8, 512, 2): (9469.2, 16384.0), (1, 4, 256, 1): (9378.6, 16384.0),
-                (2, 4, 128, 1): (9424.3, 16384.0), (1, 8, 512, 1): (9374.6, 16384.0),
-                (1, 6, 512, 1): (9355.2, 16384.0)},
+    "source": "17e1e7c81cc6", "fetch_scale": 2.0, "write_scale": 1.0,
+    "traffic": {(2, 16, 512, 4): (9888.8, 16384.0)},
     "fp64_flops_hw": {
         ("fp64-4096x128", 2, 16, 512, 4): 373.2,
-        ("fp64-4096x128", 2, 8, 256, 2): 362.5, ("fp64-4096x128", 2, 16, 512, 2): 362.5,
-        ("fp64-4096x128", 1, 8, 512, 2): 362.5, ("fp64-4096x128", 1, 4, 256, 1): 341.0,
-        ("fp64-4096x128", 2, 4, 128, 1): 341.0, ("fp64-4096x128", 1, 8, 512, 1): 341.0,
-        ("fp64-4096x128", 1, 6, 512, 1): 312.7,
-        ("dd-256x32", 1, 2, 256, 2): 5066.0, ("dd-256x32", 1, 2, 512, 2): 7802.0,
-        ("dd-256x32", 1, 4, 512, 2): 4359.7, ("dd-256x32", 1, 2, 0, 1): 2766.0,
-        ("dd-1024x64", 1, 4, 512, 2): 2880.7, ("dd-1024x64", 1, 4, 512, 1): 2414.7,
-        ("dd-1024x64", 1, 2, 256, 1): 2531.2,
-        ("qd-2048x64", 1, 4, 128, 1): 17077.4, ("qd-2048x64", 1, 8, 256, 1): 16593.9,
-        ("qd-2048x64", 1, 4, 256, 1): 19871.4,
-        ("dd-4096x128", 1, 8, 256, 1): 1844.8, ("dd-4096x128", 1, 16, 512, 1): 1815.7,
-        ("dd-4096x128", 1, 4, 256, 1): 2074.0,
-        ("qd-4096x128", 1, 8, 256, 1): 15200.7, ("qd-4096x128", 1, 4, 256, 1): 17081.2,
+        ("fp64-256x32", 1, 4, 512, 4): 959.5,
+        ("dd-256x32", 1, 2, 256, 2): 5066.0,
+        ("dd-1024x64", 1, 4, 512, 2): 2880.7,
+        ("dd-4096x128", 1, 8, 256, 1): 1844.8,
+        ("qd-2048x64", 1, 4, 128, 1): 17077.4,
         ("qd-4096x128", 1, 16, 256, 1): 14260.5,
+    },
+    "fp64_mix": {
+        ("fp64-4096x128", 2, 16, 512, 4): (40.2, 60.6, 134.7, 2.9),
+        ("fp64-256x32", 1, 4, 512, 4): (101.5, 153.8, 348.5, 7.2),
+        ("dd-256x32", 1, 2, 256, 2): (3074.0, 336.0, 828.0, 0.0),
+        ("dd-1024x64", 1, 4, 512, 2): (1771.3, 191.9, 458.8, 0.0),
+        ("dd-4096x128", 1, 8, 256, 1): (1136.9, 123.0, 292.4, 0.0),
+        ("qd-2048x64", 1, 4, 128, 1): (14249.5, 830.7, 998.6, 0.0),
+        ("qd-4096x128", 1, 16, 256, 1): (11942.7, 684.6, 816.6, 0.0),
     },
 }
 
@@ -99,8 +91,11 @@ def _torch():
 
 def graph_length(graph, steps):
     """Steps per captured graph for a timed run of `steps`: the requested
-    length, but no longer than the run, so that the timed steps replay graphs."""
-    return min(graph, steps) if graph else 0
+    length when the run holds at least one such graph, else no graph (a run
+    shorter than one graph is a handful of launches, which a graph replay does
+    not make faster: measured on the headline, 20 steps took 12.2 us per step
+    as plain launches and 12.5 as one replay)."""
+    return graph if graph and steps >= graph else 0
 
 
 def time_single(T, w, fields, steps, warmup, graph, tile, torch, stream, log=None, fixed_shape=None,

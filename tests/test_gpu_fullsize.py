@@ -121,3 +121,47 @@ def test_headline_grid_window_parity(w, tmp_path, monkeypatch):
     print("  rel Linf over the %d x %d window = %.3e (tolerance %.0e)" % (2 * half + 1, w.n_theta, rel,
                                                                          TOL[w.words]), flush=True)
     assert mx > 0 and rel <= TOL[w.words]
+
+
+# (workload, higher precision): the same run in more words is within a small
+# multiple of its own tolerance of the exact scheme (the sampled points above
+# pin the higher-precision runs against the oracle), so the difference bounds
+# the lower-precision result's error at every grid point
+HIGHER = [(inputs.C2, 2), (inputs.C3_PARITY, 4)]
+
+
+@pytest.mark.parametrize("w,words_hi", HIGHER, ids=["%s-vs-%dw" % (x[0].name, x[1]) for x in HIGHER])
+def test_full_grid_against_higher_precision(w, words_hi):
+    """Every point of every field after the workload's full step count, in the
+    default launch shape with graphs, against the same workload run in more
+    words: rel L-infinity within the lower precision's tolerance."""
+    import numpy as np
+    print("full grid %s (%d steps) against %d words" % (w.name, w.steps, words_hi), flush=True)
+    out = {}
+    for words in (w.words, words_hi):
+        wx = w.with_(words=words)
+        h = T.Teuk(wx.s, wx.m, wx.a_over_M, T.make_grid(wx.n_r, wx.n_theta, wx.rstar_min, wx.rstar_max, wx.cfl,
+                                                       wx.mass, wx.angular_order), words)
+        h.use_graph(100)
+        h.set_initial(*inputs.initial_fields(wx))
+        h.step(wx.steps)
+        out[words] = [h.read_field(c) for c in range(4)]
+        h.close()
+    lo, hi = out[w.words], out[words_hi]
+    # difference of the word expansions, leading words first: the leading
+    # difference is exact (Sterbenz) where the values are close, and each
+    # later term adds a rounding error of order 2^-53 of itself, far below
+    # the tolerance
+    err, mx = 0.0, 0.0
+    for c in range(4):
+        a = lo[c].reshape(-1, w.words)
+        b = hi[c].reshape(-1, words_hi)
+        d = a[:, 0] - b[:, 0]
+        for k in range(1, words_hi):
+            d = d + ((a[:, k] if k < w.words else 0.0) - b[:, k])
+        err = max(err, float(np.max(np.abs(d))))
+        mx = max(mx, float(np.max(np.abs(b[:, 0]))))
+    rel = err / mx
+    print("  rel Linf over all %d points = %.3e (tolerance %.0e)" % (w.n_r * w.n_theta, rel, TOL[w.words]),
+          flush=True)
+    assert rel <= TOL[w.words]

@@ -96,12 +96,13 @@ def test_bench_counter_tables_follow_the_kernel_sources(monkeypatch):
         assert len(key) == 5 and key[4] in (1, 2, 4)
 
 
-def test_graph_length_makes_the_timed_steps_graph_replays():
+def test_graph_length_covers_whole_graphs_only():
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.graph_length(100, 20) == 20          # a short timed run is one replay
+    assert bench.graph_length(100, 20) == 0           # shorter than one graph: plain launches
+    assert bench.graph_length(100, 100) == 100
     assert bench.graph_length(100, 10000) == 100
-    assert bench.graph_length(0, 20) == 0
+    assert bench.graph_length(0, 20000) == 0
 
 
 def test_issue_ceiling_from_the_instruction_mix(monkeypatch):
