@@ -41,14 +41,14 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 #    from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 in the same way.  Key as
 #    fp64_flops_hw.
 MEASURED = {
-    "source": "17e1e7c81cc6", "fetch_scale": 2.0, "write_scale": 1.0,
+    "source": "53de0516d14d", "fetch_scale": 2.0, "write_scale": 1.0,
     "traffic": {(2, 16, 512, 4): (9888.8, 16384.0)},
     "fp64_flops_hw": {
         ("fp64-4096x128", 2, 16, 512, 4): 373.2,
         ("fp64-256x32", 1, 4, 512, 4): 959.5,
         ("dd-256x32", 1, 2, 256, 2): 5066.0,
         ("dd-1024x64", 1, 4, 512, 2): 2880.7,
-        ("dd-4096x128", 1, 8, 256, 1): 1844.8,
+        ("dd-4096x128", 1, 8, 256, 1): 1829.8,
         ("qd-2048x64", 1, 4, 128, 1): 17077.4,
         ("qd-4096x128", 1, 16, 256, 1): 14260.5,
     },
@@ -57,7 +57,7 @@ MEASURED = {
         ("fp64-256x32", 1, 4, 512, 4): (101.5, 153.8, 348.5, 7.2),
         ("dd-256x32", 1, 2, 256, 2): (3074.0, 336.0, 828.0, 0.0),
         ("dd-1024x64", 1, 4, 512, 2): (1771.3, 191.9, 458.8, 0.0),
-        ("dd-4096x128", 1, 8, 256, 1): (1136.9, 123.0, 292.4, 0.0),
+        ("dd-4096x128", 1, 8, 256, 1): (1121.9, 123.0, 292.4, 0.0),
         ("qd-2048x64", 1, 4, 128, 1): (14249.5, 830.7, 998.6, 0.0),
         ("qd-4096x128", 1, 16, 256, 1): (11942.7, 684.6, 816.6, 0.0),
     },
@@ -302,7 +302,9 @@ def main():
     if not args.headline_only:
         log("bench: FP64 FMA probe")
         out["fp64_fma_probe"] = fma_probe(T)
-        per = {"fp64-4096x128": {"words": 1, "steps": args.steps, "updates_per_s": value,
+        per = {"fp64-4096x128": {"words": 1, "steps": args.steps, "updates_per_s": value, "ms_per_step": ms_step,
+                                 "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1],
+                                 "block": shape[2], "steps_per_launch": shape[3], "graph_replays_timed": replays,
                                  "pct_fp64_peak": out["pct_fp64_peak"],
                                  "pct_fp64_peak_hw": out["pct_fp64_peak_hw"],
                                  "issue_ceiling_frac": out["issue_ceiling_frac"],

@@ -942,26 +942,63 @@ __device__ __forceinline__ void xput_ghosted(d2 *slot, int rs, int j, int nth, c
     if (j >= nth - kMaxReach) xput<T>(slot, rs, kMaxReach + 2 * nth - 1 - j, v);
 }
 
-// angular operator at row j from a ghosted slot (see theta_stencil)
+// angular operator at row j from a ghosted slot (see theta_stencil).
+// wmp: double-double weights of row j held in registers (taps -kMaxReach ..
+// kMaxReach, zero beyond the reach), or nullptr to load them per tap.
 template <class T>
 __device__ __forceinline__ cx<T> stencil_ghosted(const d2 *slot, int rs, int j, int nth, int reach,
-                                                 const GLB double *__restrict__ wt, const double *w) {
+                                                 const GLB double *__restrict__ wt, const double *w,
+                                                 const T *wmp = nullptr) {
     constexpr int W = words_of<T>::value;
     Acc<T> re, im;
-    if constexpr (W == 1) {
+    if (W == 2 && wmp) {
+        // all eleven taps, in order; taps beyond the reach have weight 0 and
+        // read a valid ghosted row, their exact zero products change nothing
+#pragma unroll
+        for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
+            const cx<T> x = xget<T>(slot, rs, j + k);      // row j + k - kMaxReach
+            re.prod(wmp[k], x.re);
+            im.prod(wmp[k], x.im);
+        }
+    } else if constexpr (W == 1) {
 #pragma unroll
         for (int k = 0; k < 2 * kMaxReach + 1; ++k) {
             const cx<T> x = xget<T>(slot, rs, j + k);      // row j + k - kMaxReach
             re.prod(w[k], x.re);
             im.prod(w[k], x.im);
         }
-    } else {
+    } else if constexpr (W == 2) {
+        // double-double: the weight (a global load) and the LDS value of tap
+        // k + 1 are requested before tap k is accumulated, so a tap's loads
+        // are in flight during the previous tap's arithmetic (same operations
+        // in the same order as the plain loop)
+        const GLB double *wrow = wt + (uint32_t)j;
+        cx<T> x = xget<T>(slot, rs, kMaxReach + j - reach);
+        T wk = gld<T>(wrow, (uint32_t)nth, 0u);
 #pragma unroll 1
         for (int k = -reach; k <= reach; ++k) {
-            const cx<T> x = xget<T>(slot, rs, kMaxReach + j + k);
-            const T wk = gld<T>(wt + (uint32_t)((k + reach) * W * nth), (uint32_t)nth, (uint32_t)j);
+            const bool more = k < reach;
+            const int kn = more ? k + 1 : k;
+            const cx<T> xn = xget<T>(slot, rs, kMaxReach + j + kn);
+            const T wn = gld<T>(wrow + (uint32_t)((kn + reach) * W * nth), (uint32_t)nth, 0u);
             re.prod(wk, x.re);
             im.prod(wk, x.im);
+            x = xn;
+            wk = wn;
+        }
+    } else {
+        // quad-double: the weight of tap k + 1 (a global load) is requested
+        // before tap k is accumulated; its LDS value is read in the tap itself
+        const GLB double *wrow = wt + (uint32_t)j;
+        T wk = gld<T>(wrow, (uint32_t)nth, 0u);
+#pragma unroll 1
+        for (int k = -reach; k <= reach; ++k) {
+            const int kn = k < reach ? k + 1 : k;
+            const T wn = gld<T>(wrow + (uint32_t)((kn + reach) * W * nth), (uint32_t)nth, 0u);
+            const cx<T> x = xget<T>(slot, rs, kMaxReach + j + k);
+            re.prod(wk, x.re);
+            im.prod(wk, x.im);
+            wk = wn;
         }
     }
     return {re.result(), im.result()};
@@ -1106,6 +1143,21 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
             wreg[k] = (lane_on && kk >= -R && kk <= R) ? wtab[(uint32_t)((kk + R) * nth + j)] : 0.0;
         }
     }
+    // double-double forms that run two wavefronts per SIMD with or without them
+    // (the loop form, and two unrolled iterations with fused steps): the row's
+    // eleven weights in registers for the whole launch instead of one global
+    // load per tap and stencil.  The forms at three wavefronts per SIMD keep the
+    // loads (the 44 extra VGPRs would cost them a wavefront).
+    constexpr bool WMP = W == 2 && (TM == 0 || (TM == 2 && NS > 1));
+    T wmp[WMP ? 2 * RM + 1 : 1];
+    if constexpr (WMP) {
+#pragma unroll
+        for (int k = 0; k < 2 * RM + 1; ++k) {
+            const int kk = k - RM;
+            wmp[k] = (kk >= -R && kk <= R) ? gld<T>(wtab + (uint32_t)((kk + R) * W * nth), (uint32_t)nth, (uint32_t)jj)
+                                           : mp_from<T>(0.0);
+        }
+    }
     const Pt<T> zero = {{mp_from<T>(0.0), mp_from<T>(0.0)}, {mp_from<T>(0.0), mp_from<T>(0.0)}};
     if (lane_on && g == 0) {
         if (c0 == 0) gst_pt(uout, plane, (uint32_t)j, zero);
@@ -1185,7 +1237,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         if (t == TI) return false;
         cx<T> l_c[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) l_c[p] = stencil_ghosted<T>(xp + p * CH * RS, RS, jj, nth, R, wtab, wreg);
+        for (int p = 0; p < P; ++p)
+            l_c[p] = stencil_ghosted<T>(xp + p * CH * RS, RS, jj, nth, R, wtab, wreg, WMP ? wmp : nullptr);
         if (last_on) xput<T>(XL + sn, nth, j, l_c[P - 1]);
         Pt<T> u_m1;                                 // u^n left of the run
         u_m1.phi = xget<T>(XP + slo + (P - 1) * CH * RS, RS, RM + jj);
@@ -1223,7 +1276,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
         __syncthreads();                                                        // B3
         cx<T> lh[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) lh[p] = stencil_ghosted<T>(xh + p * CH * RS, RS, jj, nth, R, wtab, wreg);
+        for (int p = 0; p < P; ++p)
+            lh[p] = stencil_ghosted<T>(xh + p * CH * RS, RS, jj, nth, R, wtab, wreg, WMP ? wmp : nullptr);
         if (last_on && k0 + P - 1 >= 1) xput<T>(XLH + sn, nth, j, lh[P - 1]);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
