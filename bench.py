@@ -89,6 +89,24 @@ def _torch():
     return torch
 
 
+SWEEP_NAMES = ["segment", "wide", "wide2", "slab"]
+SLAB = 3
+SLAB_MAX_STEPS = 4096           # steps of one slab launch at most (the library's limit)
+
+
+def launch_steps(shape, steps):
+    """Steps one launch of this shape advances in a run of `steps`: the fused
+    count, or for the persistent slab sweep the whole call (up to its limit)."""
+    return min(steps, SLAB_MAX_STEPS) if shape[0] == SLAB else shape[3]
+
+
+def kernel_name(shape, ns, nth):
+    if shape[0] == SLAB:       # block, columns per lane = segcols / (block / n_theta)
+        return "lw_slab_kernel<%d,%d> (persistent, %d steps per launch)" % (shape[2], shape[1] * nth // shape[2], ns)
+    return (["lw_step_kernel<double>", "lw_wide_kernel<double,run 1>", "lw_wide_kernel<double,run 2>"][shape[0]]
+            + ("" if ns == 1 else " (%d steps per launch)" % ns))
+
+
 def graph_length(graph, steps):
     """Steps per captured graph for a timed run of `steps`: the requested
     length when the run holds at least one such graph, else no graph (a run
@@ -260,12 +278,12 @@ def main():
     value = pts * args.steps / (ms / 1e3)
     ms_step = ms / args.steps
     bpu = opcount.bytes_per_update(1)
-    ns = shape[3]                       # steps per launch
+    ns = launch_steps(shape, args.steps)  # steps per launch
     launch_s = ms_step * ns / 1e3       # one launch advances ns steps
     achieved = bpu * pts * ns / launch_s / 1e9
     fpu = opcount.flops_per_update(1)
     traffic = traffic_bytes = None
-    kib = measured("traffic", shape)
+    kib = measured("traffic", tuple(shape[:3]) + (ns,))
     if kib:
         traffic_bytes = 1024.0 * (kib[0] * MEASURED["fetch_scale"] + kib[1] * MEASURED["write_scale"])
         traffic = traffic_bytes / launch_s / 1e9
@@ -280,14 +298,12 @@ def main():
                    "n_r": w.n_r, "n_theta": w.n_theta, "words": 1,
                    "graph_steps": graph_length(args.graph, args.steps), "graph_replays_timed": replays,
                    "timed_steps_in_graphs": gsteps,
-                   "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1], "block": shape[2],
-                   "steps_per_launch": shape[3]},
+                   "sweep": SWEEP_NAMES[shape[0]], "segcols": shape[1], "block": shape[2],
+                   "steps_per_launch": ns},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_bytes,
-                     "kernel": ["lw_step_kernel<double>", "lw_wide_kernel<double,run 1>",
-                                "lw_wide_kernel<double,run 2>"][shape[0]]
-                               + ("" if ns == 1 else " (%d steps per launch)" % ns),
+                     "kernel": kernel_name(shape, ns, w.n_theta),
                      "algorithmic_bytes_per_update": bpu, "updates_per_launch": pts * ns,
                      "steps_per_launch": ns, "launch_us": launch_s * 1e6},
         "fp64_flops_per_update": fpu,
@@ -303,8 +319,8 @@ def main():
         log("bench: FP64 FMA probe")
         out["fp64_fma_probe"] = fma_probe(T)
         per = {"fp64-4096x128": {"words": 1, "steps": args.steps, "updates_per_s": value, "ms_per_step": ms_step,
-                                 "sweep": ["segment", "wide", "wide2"][shape[0]], "segcols": shape[1],
-                                 "block": shape[2], "steps_per_launch": shape[3], "graph_replays_timed": replays,
+                                 "sweep": SWEEP_NAMES[shape[0]], "segcols": shape[1],
+                                 "block": shape[2], "steps_per_launch": ns, "graph_replays_timed": replays,
                                  "pct_fp64_peak": out["pct_fp64_peak"],
                                  "pct_fp64_peak_hw": out["pct_fp64_peak_hw"],
                                  "issue_ceiling_frac": out["issue_ceiling_frac"],
@@ -318,8 +334,8 @@ def main():
             f = opcount.flops_per_update(wx.words)
             fh = measured("fp64_flops_hw", (wx.name,) + tuple(shp))
             per[wx.name] = {"words": wx.words, "steps": wx.steps, "updates_per_s": ups,
-                            "ms_per_step": msx / wx.steps, "sweep": ["segment", "wide", "wide2"][shp[0]],
-                            "segcols": shp[1], "block": shp[2], "steps_per_launch": shp[3],
+                            "ms_per_step": msx / wx.steps, "sweep": SWEEP_NAMES[shp[0]],
+                            "segcols": shp[1], "block": shp[2], "steps_per_launch": launch_steps(shp, wx.steps),
                             "graph_replays_timed": rpx,
                             "fp64_flops_per_update": f,
                             "pct_fp64_peak": 100.0 * f * ups / (FP64_VECTOR_PEAK_TFLOPS * 1e12),

@@ -41,6 +41,9 @@
  *
  * Environment (read when a handle is created; for tests):
  *   TEUK_FAULT=alloc      creation fails with TEUK_ENOMEM after validation;
+ *   TEUK_FAULT=slab-abort every wait of every slab-sweep launch gives up at
+ *                         once (the kernel ends early, the handle fails with
+ *                         TEUK_EDEVICE at its next synchronising call);
  *   TEUK_NO_SCALAR_ROWS   the FP64 wide sweeps stage the radial coefficient
  *                         rows in LDS even where scalar loads could serve them
  *                         (same results, bitwise).
@@ -57,7 +60,7 @@ extern "C" {
 typedef enum { TEUK_FP64 = 1, TEUK_DD = 2, TEUK_QD = 4 } teuk_precision; /* value = words per real */
 typedef enum { TEUK_PHI_RE = 0, TEUK_PHI_IM = 1, TEUK_PI_RE = 2, TEUK_PI_IM = 3 } teuk_field;
 /* r* sweep of the step kernel (see teuk_set_sweep) */
-enum { TEUK_SWEEP_SEGMENT = 0, TEUK_SWEEP_WIDE = 1, TEUK_SWEEP_WIDE2 = 2 };
+enum { TEUK_SWEEP_SEGMENT = 0, TEUK_SWEEP_WIDE = 1, TEUK_SWEEP_WIDE2 = 2, TEUK_SWEEP_SLAB = 3 };
 
 enum {
     TEUK_OK = 0,
@@ -154,7 +157,26 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
  *   segcols nodes in turn and pass neighbouring values through LDS, so each
  *   column is computed once;
  * TEUK_SWEEP_WIDE2: the same with each lane taking two neighbouring columns
- *   per turn (FP64 only; TEUK_ENOTSUP otherwise).
+ *   per turn (FP64 only; TEUK_ENOTSUP otherwise);
+ * TEUK_SWEEP_SLAB: one persistent launch per call (at most 4096 steps each;
+ *   cut where an observer record falls due): each block keeps its segment
+ *   of segcols nodes in registers and LDS for all of the launch's steps and
+ *   exchanges only the edge values with the neighbouring blocks through
+ *   global memory and flags, so no column is computed twice and no launch
+ *   falls between steps (Sec. "Teukolsky Code": the step needs one
+ *   neighbour on each side in r*).  FP64 with per-point coefficients, one
+ *   instance, n_theta a multiple of 64, one step per launch setting
+ *   (teuk_set_fuse 1); block 128..1024 threads and a multiple of n_theta
+ *   (default: the largest such block of at most 4 n_theta threads), and
+ *   segcols 1, 2 or 4 times block / n_theta; every block must be
+ *   resident at once (cooperative launch), else TEUK_ENOTSUP.  With the
+ *   default block a segment length that does not fit is replaced by the
+ *   shortest that does (teuk_set_launch with a block asks for exactly that
+ *   shape).  No graphs are
+ *   captured for it.  A wait for a neighbouring block that does not end
+ *   (about a second) makes the kernel end early and the handle fail with
+ *   TEUK_EDEVICE at its next synchronising call.  teuk_set_coefficients on
+ *   a handle using it falls back to the default sweep.
  * -1 restores the default: wide, or segment where the wide sweep's exchange
  * slots would exceed 64 KiB of LDS (large n_theta in dd and qd).  Resets the
  * block size to the default.  teuk_get_sweep returns the sweep in use. */

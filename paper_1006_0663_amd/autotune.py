@@ -9,19 +9,23 @@ file).  The launch shape does not change results (tested bitwise), only speed.
 import json
 import os
 
-SEGMENT, WIDE, WIDE2 = 0, 1, 2
+SEGMENT, WIDE, WIDE2, SLAB = 0, 1, 2, 3
 
 # (sweep, segcols, block, steps per launch) per precision (words); block 0 =
 # library default.  Fused launches (2 or 4 steps) pay off on small grids,
 # where one step does not fill the chip and launch overhead dominates, and on
 # the 4096 x 128 FP64 grid (runs of two columns: segments of 16 with four
-# steps or of 8 with two; runs of one: segments of 8, blocks of 512).
+# steps or of 8 with two; runs of one: segments of 8, blocks of 512).  The
+# persistent slab sweep (FP64, n_theta a multiple of 64, every block resident
+# at once) takes a call's steps in one launch; shapes whose blocks do not all
+# fit on the device are refused by the library and skipped.
 CANDIDATES = {
     1: [(WIDE, s, b, 1) for b in (128, 256, 512) for s in (4, 6, 8, 12, 16, 24)]
        + [(WIDE2, s, b, 1) for b in (128, 256, 512) for s in (4, 6, 8, 10, 16, 22)]
        + [(SEGMENT, 4, 256, 1), (SEGMENT, 8, 256, 1)]
        + [(WIDE, s, b, f) for f in (2, 4) for b in (256, 512) for s in (2, 4)]
-       + [(WIDE, s, 512, 2) for s in (6, 8)] + [(WIDE2, 8, 256, 2), (WIDE2, 16, 512, 2), (WIDE2, 16, 512, 4)],
+       + [(WIDE, s, 512, 2) for s in (6, 8)] + [(WIDE2, 8, 256, 2), (WIDE2, 16, 512, 2), (WIDE2, 16, 512, 4)]
+       + [(SLAB, s, b, 1) for b, s in ((256, 4), (256, 8), (512, 8), (512, 16), (1024, 16), (1024, 32))],
     2: [(WIDE, s, b, 1) for b in (0, 256, 512) for s in (2, 4, 6, 8, 12, 16)]
        + [(WIDE, s, 512, 1) for s in (24, 32)]
        + [(SEGMENT, 2, 0, 1), (SEGMENT, 2, 128, 1)]

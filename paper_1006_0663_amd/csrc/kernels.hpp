@@ -1329,4 +1329,268 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
     }
 }
 
+// ------------------------------------------------------------------ slab sweep (persistent)
+// One launch advances n steps of one FP64 instance with per-point
+// coefficients.  Block b owns the r* segment xcd_segment(b, nseg) of B = G R
+// nodes [c0, c0 + B) for the whole launch: group g (n_theta lanes, one per
+// theta row) holds the R columns c0 + gR .. c0 + gR + R - 1 in registers, and
+// Phi of every column also sits in LDS (with reflected ghost rows) for the
+// angular stencil.  Only two values per row cross a segment edge per step,
+// through global memory, each signalled by a per-wavefront flag holding the
+// tag of the step it belongs to:
+//   E1 (to the right neighbour): u^n and L(Phi^n) at the segment's last node,
+//       the left operands of the neighbour's first half node;
+//   E2 (to the left neighbour): the half step and its L at the segment's
+//       first half node c0 - 1/2, the right operands of the neighbour's last
+//       node.
+// A step has four phases, each closed by a barrier:
+//   1. L(Phi^n) of the lane's R columns to LDS (the group's last column
+//      first: the last group stores it as E1 right away and sets the flag at
+//      the end of the phase); Pi^n of that column to LDS.
+//   2. Stage 1 at the R half nodes left of the columns.  The first takes u^n
+//      and L left of the group from the group to the left, or for group 0
+//      from E1 of the left neighbour (waiting for its flag).  Half-step Phi to
+//      LDS.
+//   3. L of the half steps to LDS (group 0 stores its first half node as E2
+//      right away, flag at the end of the phase); half-step Pi of the group's
+//      first half node to LDS.
+//   4. Stage 2 at the R nodes.  The last takes the half step right of it from
+//      the group to the right, or for the last group from E2 of the right
+//      neighbour (waiting).  Radial boundary nodes are reset to zero;
+//      Phi^{n+1} to LDS.
+// Each operand is the value the other sweeps use and every point takes the
+// same operations in the same order, so the results are bitwise equal to
+// theirs; no column is computed twice and no launch boundary falls between
+// steps.  Exchange buffers alternate with the parity of the tag: a neighbour
+// can rewrite a buffer two steps later only after it has waited for data this
+// block produces after reading it.
+//
+// Every block must be resident at once (the host launches cooperatively).
+// A wait polls at most `spin` times; a wave that gives up sets *err, every
+// other wait returns as soon as it sees *err, and the blocks leave the step
+// loop after the next barrier, so the kernel always ends; the host turns a
+// nonzero *err into an error.
+//
+// Memory ordering across XCDs (each has its own L2) without cache-wide
+// fences: every exchanged double and every flag is a relaxed atomic access
+// at agent scope, which the hardware performs at the agent's coherence point
+// (never from or into a non-coherent cached copy).  The producer waits for
+// its data stores to complete (s_waitcnt) before it stores the flag; the
+// consumer issues its data loads only after its flag load has returned the
+// tag.  So the data a consumer reads are at least as new as the flag it saw.
+// The agent-scope release and acquire fences would add an L2 write-back and
+// an L2 invalidation per exchange: about 15 us per step on the 4096 x 128
+// grid, measured, against 8.4 us for the whole step without them.
+struct SlabArgs {
+    const double *uin;
+    double *uout;
+    const double *rf, *rh, *trig, *wt;
+    double *xbuf;                       // [2 parities][2: E1, E2][nseg][6][n_theta]
+    unsigned long long *flags;          // [nseg][2: E1, E2][n_theta / 64], kSlabFlagPad apart
+    int *err;
+    long long base;                     // tag of the step before the launch's first
+    long long spin;                     // polls before a wait gives up
+    int nr, nth, nseg, reach, nsteps;
+    double hdt, dt;
+};
+constexpr int kSlabFlagPad = 16;        // 128 bytes between flags
+
+__device__ __forceinline__ unsigned long long *slab_flag(const SlabArgs &A, int seg, int dir, int wv) {
+    return A.flags + ((size_t)(seg * 2 + dir) * (size_t)(A.nth >> 6) + (size_t)wv) * kSlabFlagPad;
+}
+
+// Wait (all lanes of a wavefront, same flag) until the flag holds `tag` or
+// later.  false: *err was set, or `spin` polls passed (this wave then sets
+// *err).  The signal fence keeps the compiler from moving the caller's data
+// loads above the poll.
+__device__ __forceinline__ bool slab_wait(unsigned long long *flag, unsigned long long tag, int *err, long long spin) {
+    for (long long it = 0;; ++it) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tag) break;
+        if (it >= spin) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return true;
+}
+
+__device__ __forceinline__ void slab_st(double *p, double v) {
+    __hip_atomic_store((unsigned long long *)p, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double slab_ld(double *p) {
+    return __builtin_bit_cast(double, __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Store a row's six doubles (component-major, n_theta apart).
+__device__ __forceinline__ void slab_put(double *dst, int nth, int j, const Pt<double> &u, const cx<double> &l) {
+    slab_st(dst + 0 * nth + j, u.phi.re);
+    slab_st(dst + 1 * nth + j, u.phi.im);
+    slab_st(dst + 2 * nth + j, u.pi.re);
+    slab_st(dst + 3 * nth + j, u.pi.im);
+    slab_st(dst + 4 * nth + j, l.re);
+    slab_st(dst + 5 * nth + j, l.im);
+}
+// After the wave's slab_put: wait until its stores have completed, then lane
+// 0 sets the flag to `tag`.
+__device__ __forceinline__ void slab_signal(unsigned long long *flag, unsigned long long tag, int j) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);      // every counter of the wave at zero: the stores have completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if ((j & 63) == 0) __hip_atomic_store(flag, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void slab_take(double *src, int nth, int j, Pt<double> &u, cx<double> &l) {
+    u.phi = {slab_ld(src + 0 * nth + j), slab_ld(src + 1 * nth + j)};
+    u.pi = {slab_ld(src + 2 * nth + j), slab_ld(src + 3 * nth + j)};
+    l = {slab_ld(src + 4 * nth + j), slab_ld(src + 5 * nth + j)};
+}
+
+// LDS bytes of the slab kernel: Phi^n and half-step Phi of the B columns
+// (ghosted), L of both for every column, Pi^n and half-step Pi of one column
+// per group
+MPA size_t slab_lds_bytes(int nt, int nth, int r) {
+    const int G = nt / nth, B = G * r, RS = nth + 2 * kMaxReach;
+    return sizeof(d2) * (2 * (size_t)B * RS + 2 * (size_t)B * nth + 2 * (size_t)G * nth);
+}
+
+// NT threads = G groups of n_theta (a multiple of 64) lanes; R columns per
+// lane.  A lane keeps u^n and the half step of its R columns in registers;
+// the angular operator of every column goes to LDS, where the lane and its
+// neighbours read it back.
+template <int NT, int R>
+__global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
+    constexpr int RM = kMaxReach;
+    extern __shared__ d2 xs[];
+    __shared__ int stop;
+    const int nth = A.nth, nr = A.nr, G = NT / nth, B = G * R, RS = nth + 2 * RM;
+    const int g = threadIdx.x / nth, j = threadIdx.x - g * nth, wv = j >> 6;
+    const int seg = xcd_segment(blockIdx.x, A.nseg);
+    const int c0 = seg * B, kg = g * R;
+    const bool has_l = seg > 0, has_r = seg + 1 < A.nseg;
+    d2 *const XP = xs;                  // Phi^n              [B][RS]
+    d2 *const XH = XP + B * RS;         // half-step Phi      [B][RS]
+    d2 *const XL = XH + B * RS;         // L(Phi^n)           [B][nth]
+    d2 *const XLH = XL + B * nth;       // L(half-step Phi)   [B][nth]
+    d2 *const EU = XLH + B * nth;       // Pi^n of each group's last column       [G][nth]
+    d2 *const HU = EU + G * nth;        // half-step Pi of each group's first half node
+    const uint32_t plane = (uint32_t)nr * nth;
+    const GLB double *wtab = gptr(A.wt);
+    const int reach = A.reach;
+    const double hdt = A.hdt, dt = A.dt;
+    const double cs_j = gptr(A.trig)[j], s2_j = gptr(A.trig)[nth + j];
+    double wreg[2 * RM + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * RM + 1; ++k) {
+        const int kk = k - RM;
+        wreg[k] = (kk >= -reach && kk <= reach) ? wtab[(uint32_t)((kk + reach) * nth + j)] : 0.0;
+    }
+    const Pt<double> zero = {{0.0, 0.0}, {0.0, 0.0}};
+    Pt<double> u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = c0 + kg + r;
+        u[r] = i < nr ? gld_pt<double>(gptr(A.uin), plane, (uint32_t)(i * nth + j)) : zero;
+        xput_ghosted<double>(XP + (kg + r) * RS, RS, j, nth, u[r].phi);
+    }
+    // radial row of node (or half node) i, wave-uniform: scalar loads
+    auto row = [&](bool half, int i) {
+        const int iu = __builtin_amdgcn_readfirstlane(i);
+        return (const CNS double *)(half ? A.rh : A.rf) + iu * kRadRow;
+    };
+    if (threadIdx.x == 0) stop = 0;
+    __syncthreads();
+    for (int s = 0; s < A.nsteps; ++s) {
+        const unsigned long long tag = (unsigned long long)(A.base + s + 1);
+        const size_t xo = (size_t)(tag & 1) * 2 * A.nseg * 6 * nth;
+        double *const x1 = A.xbuf + xo, *const x2 = A.xbuf + xo + (size_t)A.nseg * 6 * nth;
+        // 1. L(Phi^n) to LDS, the group's last column first (the last group
+        //    publishes it as E1 before the other columns); Pi^n of that column
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = R - 1 - q;
+            const cx<double> l = stencil_ghosted<double>(XP + (kg + r) * RS, RS, j, nth, reach, wtab, wreg);
+            xput<double>(XL + (kg + r) * nth, 0, j, l);
+            if (q == 0 && g == G - 1 && has_r) slab_put(x1 + (size_t)seg * 6 * nth, nth, j, u[R - 1], l);
+        }
+        xput<double>(EU + g * nth, 0, j, u[R - 1].pi);
+        if (g == G - 1 && has_r) slab_signal(slab_flag(A, seg, 0, wv), tag, j);
+        __syncthreads();
+        // 2. stage 1 at the half nodes c0 + kg + r - 1/2 (half index c0 + kg + r - 1)
+        Pt<double> ua = zero;
+        cx<double> la = zero.phi;
+        if (g > 0) {
+            ua.phi = xget<double>(XP + (kg - 1) * RS, RS, RM + j);
+            ua.pi = xget<double>(EU + (g - 1) * nth, 0, j);
+            la = xget<double>(XL + (kg - 1) * nth, 0, j);
+        } else if (has_l) {
+            if (slab_wait(slab_flag(A, seg - 1, 0, wv), tag, A.err, A.spin))
+                slab_take(x1 + (size_t)(seg - 1) * 6 * nth, nth, j, ua, la);
+            else
+                stop = 1;
+        }
+        Pt<double> uh[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            // (half node -1/2 of the first segment and those past the right
+            // boundary do not exist: computed with clamped rows, never used)
+            const int k = kg + r, hc = min(max(c0 + k - 1, 0), nr - 2);
+            const Pt<double> &left = r == 0 ? ua : u[r > 0 ? r - 1 : 0];
+            const cx<double> ll = r == 0 ? la : xget<double>(XL + (k - 1) * nth, 0, j);
+            const cx<double> lc = xget<double>(XL + k * nth, 0, j);
+            const Pt<double> bar = pt_avg(left, u[r]);
+            uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), row(true, hc), cs_j, s2_j, hdt);
+            xput_ghosted<double>(XH + k * RS, RS, j, nth, uh[r].phi);
+        }
+        __syncthreads();
+        if (stop) break;
+        // 3. L of the half steps to LDS, the group's first half node first
+        //    (group 0 publishes it as E2 before the others); half-step Pi of it
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const cx<double> lh = stencil_ghosted<double>(XH + (kg + r) * RS, RS, j, nth, reach, wtab, wreg);
+            xput<double>(XLH + (kg + r) * nth, 0, j, lh);
+            if (r == 0 && g == 0 && has_l) slab_put(x2 + (size_t)seg * 6 * nth, nth, j, uh[0], lh);
+        }
+        xput<double>(HU + g * nth, 0, j, uh[0].pi);
+        if (g == 0 && has_l) slab_signal(slab_flag(A, seg, 1, wv), tag, j);
+        __syncthreads();
+        // 4. stage 2 at the nodes c0 + kg + r
+        Pt<double> ub = zero;
+        cx<double> lb = zero.phi;
+        if (g < G - 1) {
+            ub.phi = xget<double>(XH + (kg + R) * RS, RS, RM + j);
+            ub.pi = xget<double>(HU + (g + 1) * nth, 0, j);
+            lb = xget<double>(XLH + (kg + R) * nth, 0, j);
+        } else if (has_r) {
+            if (slab_wait(slab_flag(A, seg + 1, 1, wv), tag, A.err, A.spin))
+                slab_take(x2 + (size_t)(seg + 1) * 6 * nth, nth, j, ub, lb);
+            else
+                stop = 1;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = kg + r, i = c0 + k, ic = min(i, nr - 1);
+            const Pt<double> &right = r == R - 1 ? ub : uh[r < R - 1 ? r + 1 : 0];
+            const cx<double> lr = r == R - 1 ? lb : xget<double>(XLH + (k + 1) * nth, 0, j);
+            const cx<double> lc = xget<double>(XLH + k * nth, 0, j);
+            const Pt<double> un = lw_stage_row(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr),
+                                               row(false, ic), cs_j, s2_j, dt);
+            u[r] = (i == 0 || i >= nr - 1) ? zero : un;
+            xput_ghosted<double>(XP + k * RS, RS, j, nth, u[r].phi);
+        }
+        __syncthreads();
+        if (stop) break;
+    }
+    if (stop) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = c0 + kg + r;
+        if (i < nr) gst_pt(gptr(A.uout), plane, (uint32_t)(i * nth + j), u[r]);
+    }
+}
+
 }  // namespace lwk

@@ -21,4 +21,39 @@ hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, cons
     coef_fp64_planes_kernel<<<grid, 64, 0, stream>>>(nr, nth, rf, rh, trig, cf, ch);
     return hipGetLastError();
 }
+
+// ---- slab sweep (lw_slab_kernel)
+template <int NT, int R>
+hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
+    const void *f = (const void *)lw_slab_kernel<NT, R>;
+    if (mode == 0) {
+        SlabArgs arg = *a;
+        void *args[] = {&arg};
+        return hipLaunchCooperativeKernel(f, dim3(nblocks), dim3(NT), args, (unsigned)lds, stream);
+    }
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, NT, lds);
+    return e;
+}
+
+template <int NT>
+hipError_t slab_nt(int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
+    switch (r) {
+        case 1: return slab_one<NT, 1>(mode, lds, a, nblocks, stream, per_cu);
+        case 2: return slab_one<NT, 2>(mode, lds, a, nblocks, stream, per_cu);
+        case 4: return slab_one<NT, 4>(mode, lds, a, nblocks, stream, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t slab_f64(int nt, int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream,
+                    int *per_cu) {
+    switch (nt) {
+        case 128: return slab_nt<128>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 256: return slab_nt<256>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 512: return slab_nt<512>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 1024: return slab_nt<1024>(r, mode, lds, a, nblocks, stream, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
 }  // namespace lwk

@@ -155,7 +155,26 @@ struct Batch {
     int *obs_idx = nullptr;          // device: plane index i * n_theta + j per point
     double *obs_ring = nullptr;      // device: obs_cap records of 1 + 2 W obs_n doubles
     long long *obs_ctr = nullptr;    // device: steps since set_initial, records written, next step due
+    // slab sweep (lw_slab_kernel): columns per lane, segments, exchange buffers,
+    // flags and error word, and the tag of the last step launched
+    int slab_r = 0, slab_nseg = 0;
+    double *slab_x = nullptr;
+    unsigned long long *slab_flags = nullptr;
+    int *slab_err = nullptr;
+    long long slab_base = 0;
+    bool slab_fault = false;         // TEUK_FAULT=slab-abort: every wait of every launch gives up
 };
+
+void free_slab(Batch &b) {
+    hipFree(b.slab_x);
+    hipFree(b.slab_flags);
+    hipFree(b.slab_err);
+    b.slab_x = nullptr;
+    b.slab_flags = nullptr;
+    b.slab_err = nullptr;
+    b.slab_r = b.slab_nseg = 0;
+    b.slab_base = 0;
+}
 
 void drop_graph(Batch &b) {
     for (int p = 0; p < 2; ++p) {
@@ -196,6 +215,7 @@ void free_batch(Batch &b) {
     b.d_inst = nullptr;
     b.d_items = nullptr;
     free_observer(b);
+    free_slab(b);
     if (b.host_state) hipHostFree(b.host_state);
     b.host_state = nullptr;
     if (b.own_stream) hipStreamDestroy(b.own_stream);
@@ -309,6 +329,103 @@ int wide_cols(int c0, int c1, int nr, int ns) {
     return e - a + 1 + ((ns > 1 && e == nr - 1) ? ns : 0);
 }
 
+// Plan of the slab sweep into the copy b (see build_worklist): block, segment
+// length, LDS, residency of every block, and zeroed exchange buffers, flags
+// and error word (allocated here; build_worklist hands them to the handle or
+// frees them).
+int plan_slab(const Batch &h, Batch &b) {
+    if (b.inst.size() != 1) return fail(TEUK_ENOTSUP, "the slab sweep advances a single instance");
+    const Instance &I = b.inst[0];
+    if (b.words != 1) return fail(TEUK_ENOTSUP, "the slab sweep is built for FP64");
+    if (!I.onfly || I.injected)
+        return fail(TEUK_ENOTSUP, "the slab sweep needs per-point coefficients (not stored or injected planes)");
+    const int nth = I.g.n_theta, nr = I.g.n_r;
+    if (nth % 64 != 0 || nth > 1024) return fail(TEUK_ENOTSUP, "the slab sweep needs n_theta a multiple of 64, at most 1024");
+    if (b.fuse != 1)
+        return fail(TEUK_EINVAL, "the slab sweep runs a call's steps in one launch: steps per launch must be 1");
+    // default block: the largest of 128..1024 threads that is a multiple of
+    // n_theta and at most 4 n_theta
+    int nt = b.nt_req;
+    for (int c = 1024; !nt && c >= 128; c /= 2)
+        if (c % nth == 0 && c <= 4 * nth) nt = c;
+    if (!nt) return fail(TEUK_ENOTSUP, "slab sweep: no block of 128..1024 threads is a multiple of n_theta");
+    if (nt < 128 || nt < nth || nt % nth != 0)
+        return fail(TEUK_EINVAL, "slab sweep: block must be 128..1024 threads and a multiple of n_theta");
+    const int G = nt / nth;
+    int dev = 0, cus = 0, coop = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e != hipSuccess) return hip_fail(e, "slab sweep: device attributes");
+    if (!coop) return fail(TEUK_ENOTSUP, "slab sweep: the device does not launch cooperatively");
+    // the requested segment length; with the default block, one that does not
+    // fit is replaced by the shortest that does (1, 2 or 4 columns per lane)
+    std::vector<int> segs{b.seg_req};
+    if (!b.nt_req)
+        for (int r : {1, 2, 4}) segs.push_back(G * r);
+    int seg = 0, r = 0, nseg = 0;
+    size_t lds = 0;
+    std::string why;
+    int why_rc = TEUK_OK;
+    for (int cand : segs) {
+        const int rc_ = cand / G;
+        if (cand % G != 0 || (rc_ != 1 && rc_ != 2 && rc_ != 4)) {
+            if (why.empty()) {
+                why = "slab sweep: segcols must be 1, 2 or 4 times block / n_theta";
+                why_rc = TEUK_EINVAL;
+            }
+            continue;
+        }
+        const size_t l = lwk::slab_lds_bytes(nt, nth, rc_);
+        if (l > (size_t)device_lds_limit()) {
+            if (why.empty()) {
+                why = "slab sweep: launch shape needs more LDS than the device has";
+                why_rc = TEUK_EINVAL;
+            }
+            continue;
+        }
+        int per_cu = 0;
+        e = lwk::slab_f64(nt, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
+        if (e != hipSuccess) return hip_fail(e, "slab sweep: occupancy");
+        const int ns = (nr + cand - 1) / cand;
+        if ((long)per_cu * cus < ns) {
+            if (why.empty()) {
+                why = "slab sweep: " + std::to_string(ns) + " segments of " + std::to_string(cand) +
+                      " nodes, but the device holds " + std::to_string((long)per_cu * cus) +
+                      " such blocks at once (use longer segments)";
+                why_rc = TEUK_ENOTSUP;
+            }
+            continue;
+        }
+        seg = cand;
+        r = rc_;
+        nseg = ns;
+        lds = l;
+        break;
+    }
+    if (!seg) return fail(why_rc, why);
+    const size_t nx = 2 * 2 * (size_t)nseg * 6 * nth, nf = (size_t)nseg * 2 * (nth / 64) * lwk::kSlabFlagPad;
+    e = hipMalloc((void **)&b.slab_x, nx * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&b.slab_flags, nf * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&b.slab_err, sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(b.slab_x, 0, nx * sizeof(double), h.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.slab_flags, 0, nf * sizeof(unsigned long long), h.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.slab_err, 0, sizeof(int), h.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h.stream);
+    if (e != hipSuccess) {
+        free_slab(b);
+        return hip_fail(e, "slab sweep: exchange buffers");
+    }
+    b.nt = nt;
+    b.segcols = seg;
+    b.lds = lds;
+    b.cmode = 2;
+    b.tm = 0;
+    b.slab_r = r;
+    b.slab_nseg = nseg;
+    return TEUK_OK;
+}
+
 // (Re)build the launch plan, the descriptors and the work list from the
 // requests (sweep, segment length, block, steps per launch) and the
 // instances; all instances must share `cur`.  Transactional: the plan is
@@ -330,7 +447,9 @@ int build_worklist(Batch &h) {
     for (auto &I : b.inst) maxnth = std::max(maxnth, I.g.n_theta);
     b.sweep = b.sweep_req >= 0 ? b.sweep_req : default_sweep(b.words);
     b.lds = 0;
-    if (b.sweep != TEUK_SWEEP_SEGMENT) {
+    if (b.sweep == TEUK_SWEEP_SLAB) {
+        if (int rc = plan_slab(h, b)) return rc;
+    } else if (b.sweep != TEUK_SWEEP_SEGMENT) {
         // FP64 per-point coefficients: radial rows by scalar loads when every
         // wavefront lies in one theta column (n_theta a multiple of 64), else
         // staged in LDS
@@ -371,7 +490,9 @@ int build_worklist(Batch &h) {
             }
         }
     }
-    if (b.sweep != TEUK_SWEEP_SEGMENT) {
+    if (b.sweep == TEUK_SWEEP_SLAB) {
+        // planned above
+    } else if (b.sweep != TEUK_SWEEP_SEGMENT) {
         // iterations a work item needs: its columns over the columns a block takes per iteration
         // (fused steps read fuse columns on each side, plus fuse columns
         // past the right domain boundary)
@@ -477,6 +598,7 @@ int build_worklist(Batch &h) {
     if (e != hipSuccess) {
         hipFree(d_inst);
         hipFree(d_items);
+        free_slab(b);
         return hip_fail(e, "descriptors and work list");
     }
     // commit (the previous arrays are no longer referenced by queued work:
@@ -492,6 +614,13 @@ int build_worklist(Batch &h) {
     h.cmode = b.cmode;
     h.tm = b.tm;
     h.lds = b.lds;
+    free_slab(h);
+    h.slab_r = b.slab_r;
+    h.slab_nseg = b.slab_nseg;
+    h.slab_x = b.slab_x;
+    h.slab_flags = b.slab_flags;
+    h.slab_err = b.slab_err;
+    h.slab_base = 0;
     drop_graph(h);
     return TEUK_OK;
 }
@@ -503,8 +632,10 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
         int rc = validate(s[k], m[k], a[k], &g[k], prec);
         if (rc != TEUK_OK) return rc;
     }
-    if (const char *f = std::getenv("TEUK_FAULT"))
+    if (const char *f = std::getenv("TEUK_FAULT")) {
         if (std::strcmp(f, "alloc") == 0) return fail(TEUK_ENOMEM, "allocation failure injected by TEUK_FAULT=alloc");
+        b.slab_fault = std::strcmp(f, "slab-abort") == 0;
+    }
     b.words = prec;
     hipError_t e = hipStreamCreateWithFlags(&b.own_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -574,6 +705,8 @@ int create_batch(Batch &b, int n, const int *s, const int *m, const double *a, c
     return build_worklist(b);
 }
 
+int slab_check(Batch &b);
+
 int check_ok(Batch &b) {
     if (b.sticky != TEUK_OK) return fail(b.sticky, "handle is in a failed state after an earlier device error");
     return TEUK_OK;
@@ -589,7 +722,7 @@ int quiesce(Batch &b) {
         b.sticky = TEUK_EDEVICE;
         return hip_fail(e, "stream synchronize");
     }
-    return TEUK_OK;
+    return slab_check(b);
 }
 
 // host interchange [j][i][w]  <->  device planar [w][i][j]
@@ -628,6 +761,7 @@ int download_planes(Batch &b, const double *dsrc, int nplanes_w, int nr, int nth
         b.sticky = TEUK_EDEVICE;
         return hip_fail(e, "download");
     }
+    if (int rc = slab_check(b)) return rc;
     (void)nplanes_w;
     const size_t plane = (size_t)nr * nth;
     for (int j = 0; j < nth; ++j)
@@ -712,10 +846,64 @@ __global__ void observer_record_kernel(const double *__restrict__ u, unsigned lo
     }
 }
 
+// Polls of one slab wait before it gives up: 2^21 polls (each a load that
+// may miss to memory, then s_sleep 2) take of the order of a second, against
+// microseconds for a step.
+constexpr long long kSlabSpin = 1ll << 21;
+// Steps of one slab launch at most (a longer call takes several launches).
+constexpr long kSlabMaxSteps = 4096;
+
+// One slab launch of `ns` steps from buffer `parity` into the other buffer.
+hipError_t slab_launch(Batch &b, int parity, int ns) {
+    const Instance &I = b.inst[0];
+    lwk::SlabArgs a{};
+    a.uin = I.u[parity];
+    a.uout = I.u[parity ^ 1];
+    a.rf = I.rf;
+    a.rh = I.rh;
+    a.trig = I.trig;
+    a.wt = I.wt;
+    a.xbuf = b.slab_x;
+    a.flags = b.slab_flags;
+    a.err = b.slab_err;
+    a.base = b.slab_base;
+    a.spin = kSlabSpin;
+    a.nr = I.g.n_r;
+    a.nth = I.g.n_theta;
+    a.nseg = b.slab_nseg;
+    a.reach = I.reach;
+    a.nsteps = ns;
+    a.hdt = I.hdt[0];
+    a.dt = I.dt[0];
+    hipError_t e = hipSuccess;
+    if (b.slab_fault) e = hipMemsetD32Async((hipDeviceptr_t)b.slab_err, 1, 1, b.stream);
+    if (e == hipSuccess) e = lwk::slab_f64(b.nt, b.slab_r, 0, b.lds, &a, b.slab_nseg, b.stream, nullptr);
+    b.slab_base += ns;
+    return e;
+}
+
+// After the handle's stream has drained: a slab launch whose wait gave up
+// puts the handle in the failed state.
+int slab_check(Batch &b) {
+    if (!b.slab_err) return TEUK_OK;
+    int v = 0;
+    const hipError_t e = hipMemcpy(&v, b.slab_err, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        b.sticky = TEUK_EDEVICE;
+        return hip_fail(e, "slab error word");
+    }
+    if (v) {
+        b.sticky = TEUK_EDEVICE;
+        return fail(TEUK_EDEVICE, "slab sweep: a wait for a neighbouring block gave up; the kernel ended early and "
+                                  "the fields are not valid");
+    }
+    return TEUK_OK;
+}
+
 // one step-kernel launch of `ns` steps from buffer `parity`, then the
 // observer record if one is set
-hipError_t launch_step(const Batch &b, int parity, int ns) {
-    hipError_t e = step_launch(b, parity, ns);
+hipError_t launch_step(Batch &b, int parity, int ns) {
+    hipError_t e = b.sweep == TEUK_SWEEP_SLAB ? slab_launch(b, parity, ns) : step_launch(b, parity, ns);
     if (e == hipSuccess && b.obs_n > 0) {
         const Instance &I = b.inst[0];
         observer_record_kernel<<<1, 256, 0, b.stream>>>(I.u[parity ^ 1], (unsigned long long)I.plane(), b.words,
@@ -727,7 +915,10 @@ hipError_t launch_step(const Batch &b, int parity, int ns) {
 }
 
 // launches of a captured step loop: about graph_steps / fuse, at least one
-int graph_launches(const Batch &b) { return b.graph_steps > 0 ? std::max(1, b.graph_steps / b.fuse) : 0; }
+// (the slab sweep runs a call's steps in one launch and takes no graph)
+int graph_launches(const Batch &b) {
+    return b.graph_steps > 0 && b.sweep != TEUK_SWEEP_SLAB ? std::max(1, b.graph_steps / b.fuse) : 0;
+}
 
 // capture the step loop that starts from state buffer `par`
 hipError_t capture_graph(Batch &b, int par) {
@@ -764,7 +955,20 @@ int do_steps(Batch &b, long n) {
     // a captured graph holds graph_launches(b) launches, and one graph is kept
     // per state buffer a replay can start from
     const int F = b.fuse;
-    if (b.host_state) {
+    if (b.sweep == TEUK_SWEEP_SLAB && !b.host_state) {
+        // launches of up to kSlabMaxSteps steps, cut where an observer record
+        // falls due
+        while (left > 0 && e == hipSuccess) {
+            long k = std::min(left, kSlabMaxSteps);
+            if (b.obs_n > 0) {
+                const long st = b.inst[0].steps + (n - left);
+                k = std::min(k, (st / b.obs_every + 1) * (long)b.obs_every - st);
+            }
+            e = launch_step(b, cur, (int)k);
+            cur ^= 1;
+            left -= k;
+        }
+    } else if (b.host_state) {
         for (; left > 0 && e == hipSuccess; --left) {
             e = launch_step(b, cur, 1);
             cur ^= 1;
@@ -810,7 +1014,7 @@ int do_steps(Batch &b, long n) {
 // capture the step loops of both starting buffers now (no steps run)
 int prepare_graph(Batch &b) {
     if (int rc = check_ok(b)) return rc;
-    if (b.graph_steps <= 0 || b.host_state) return TEUK_OK;
+    if (graph_launches(b) <= 0 || b.host_state) return TEUK_OK;
     for (int par = 0; par < 2; ++par) {
         hipError_t e = b.gexec[par] ? hipSuccess : capture_graph(b, par);
         // move the executable graph to the device now, so that its first
@@ -946,8 +1150,9 @@ static int set_launch(Batch &b, int segcols, int block) {
 }
 
 static int set_sweep(Batch &b, int sweep) {
-    if (sweep != -1 && sweep != TEUK_SWEEP_SEGMENT && sweep != TEUK_SWEEP_WIDE && sweep != TEUK_SWEEP_WIDE2)
-        return fail(TEUK_EINVAL, "sweep must be -1 (default), 0 (segment), 1 (wide) or 2 (wide, runs of two)");
+    if (sweep != -1 && sweep != TEUK_SWEEP_SEGMENT && sweep != TEUK_SWEEP_WIDE && sweep != TEUK_SWEEP_WIDE2 &&
+        sweep != TEUK_SWEEP_SLAB)
+        return fail(TEUK_EINVAL, "sweep must be -1 (default), 0 (segment), 1 (wide), 2 (wide, runs of two) or 3 (slab)");
     if (sweep == TEUK_SWEEP_WIDE2 && b.words != 1)
         return fail(TEUK_ENOTSUP, "the wide sweep with runs of two columns is built for FP64 only");
     if (int rc = quiesce(b)) return rc;
@@ -1080,14 +1285,22 @@ int teuk_set_coefficients(teuk_t *h, int which, const double *in) {
         I.cf = cf;
         I.ch = ch;
         I.onfly = 0;
-        const int old_fuse = b.fuse;
+        const int old_fuse = b.fuse, old_sweep = b.sweep_req, old_nt = b.nt_req;
         int rc = build_worklist(b);
+        if (rc != TEUK_OK && b.sweep_req == TEUK_SWEEP_SLAB) {
+            // the slab sweep needs per-point coefficients: back to the default
+            b.sweep_req = -1;
+            b.nt_req = 0;
+            rc = build_worklist(b);
+        }
         if (rc != TEUK_OK && b.fuse > 1) {
             b.fuse = 1;
             rc = build_worklist(b);
         }
         if (rc != TEUK_OK) {
             b.fuse = old_fuse;
+            b.sweep_req = old_sweep;
+            b.nt_req = old_nt;
             I.onfly = 1;
             I.cf = I.ch = nullptr;
             hipFree(cf);

@@ -22,7 +22,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--segcols", type=int, default=4)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--sweep", type=int, default=-1, help="0 segment, 1 wide, 2 wide with runs of two, -1 default")
+    ap.add_argument("--sweep", type=int, default=-1,
+                    help="0 segment, 1 wide, 2 wide with runs of two, 3 slab (persistent; --steps in one launch), "
+                         "-1 default")
     ap.add_argument("--fuse", type=int, default=1, help="steps per launch (1, 2 or 4)")
     ap.add_argument("--tuned", action="store_true", help="use the autotuner's shape (cached if tuned before)")
     ap.add_argument("--time", type=int, default=0, metavar="REPS",

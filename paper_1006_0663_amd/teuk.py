@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libteuk.so")
 
 TEUK_OK, TEUK_EINVAL, TEUK_ENOMEM, TEUK_EDEVICE, TEUK_ENOTSUP, TEUK_ENONFINITE = 0, -1, -2, -3, -4, -5
 FP64, DD, QD = 1, 2, 4
-SWEEP_SEGMENT, SWEEP_WIDE, SWEEP_WIDE2 = 0, 1, 2
+SWEEP_SEGMENT, SWEEP_WIDE, SWEEP_WIDE2, SWEEP_SLAB = 0, 1, 2, 3
 PHI_RE, PHI_IM, PI_RE, PI_IM = 0, 1, 2, 3
 
 
