@@ -165,10 +165,10 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
  *   global memory and flags, so no column is computed twice and no launch
  *   falls between steps (Sec. "Teukolsky Code": the step needs one
  *   neighbour on each side in r*).  FP64 with per-point coefficients, one
- *   instance, n_theta a multiple of 64, one step per launch setting
- *   (teuk_set_fuse 1); block 128..1024 threads and a multiple of n_theta
- *   (default: the largest such block of at most 4 n_theta threads), and
- *   segcols 1, 2 or 4 times block / n_theta; every block must be
+ *   instance, n_theta 64, 128 or 256, one step per launch setting
+ *   (teuk_set_fuse 1); block 256, 512 or 1024 threads and a multiple of
+ *   n_theta (default 4 n_theta), and segcols 1, 2 or 4 times block /
+ *   n_theta; every block must be
  *   resident at once (cooperative launch), else TEUK_ENOTSUP.  With the
  *   default block a segment length that does not fit is replaced by the
  *   shortest that does (teuk_set_launch with a block asks for exactly that

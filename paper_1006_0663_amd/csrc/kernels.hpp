@@ -1450,33 +1450,40 @@ __device__ __forceinline__ void slab_take(double *src, int nth, int j, Pt<double
 }
 
 // LDS bytes of the slab kernel: Phi^n and half-step Phi of the B columns
-// (ghosted), L of both for every column, Pi^n and half-step Pi of one column
-// per group
+// (ghosted), L of every column, Pi of one column per group (L(Phi^n) and the
+// half step's L share one array, as do Pi^n and the half-step Pi: each is
+// dead before the other is written)
 MPA size_t slab_lds_bytes(int nt, int nth, int r) {
     const int G = nt / nth, B = G * r, RS = nth + 2 * kMaxReach;
-    return sizeof(d2) * (2 * (size_t)B * RS + 2 * (size_t)B * nth + 2 * (size_t)G * nth);
+    return sizeof(d2) * (2 * (size_t)B * RS + (size_t)B * nth + (size_t)G * nth);
 }
 
-// NT threads = G groups of n_theta (a multiple of 64) lanes; R columns per
-// lane.  A lane keeps u^n and the half step of its R columns in registers;
-// the angular operator of every column goes to LDS, where the lane and its
-// neighbours read it back.
-template <int NT, int R>
+// NT threads = G groups of NTH (= n_theta, a multiple of 64) lanes; R
+// columns per lane.  A lane keeps u^n and the half step of its R columns in
+// registers; the angular operator of every column goes to LDS, where the lane
+// and its neighbours read it back.  n_theta is a template parameter so that
+// every LDS offset is an instruction immediate.
+template <int NT, int R, int NTH>
 __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
     constexpr int RM = kMaxReach;
+    static_assert(NT % NTH == 0 && NTH % 64 == 0, "groups of whole wavefronts");
     extern __shared__ d2 xs[];
     __shared__ int stop;
-    const int nth = A.nth, nr = A.nr, G = NT / nth, B = G * R, RS = nth + 2 * RM;
+    constexpr int nth = NTH, G = NT / nth, B = G * R, RS = nth + 2 * RM;
+    const int nr = A.nr;
     const int g = threadIdx.x / nth, j = threadIdx.x - g * nth, wv = j >> 6;
     const int seg = xcd_segment(blockIdx.x, A.nseg);
     const int c0 = seg * B, kg = g * R;
     const bool has_l = seg > 0, has_r = seg + 1 < A.nseg;
+    // (XL and XLH share their array, as do EU and HU: phase 1 writes XL and
+    // EU, phase 2 reads them, phase 3 writes XLH and HU, phase 4 reads them,
+    // and a barrier separates each of these)
     d2 *const XP = xs;                  // Phi^n              [B][RS]
     d2 *const XH = XP + B * RS;         // half-step Phi      [B][RS]
     d2 *const XL = XH + B * RS;         // L(Phi^n)           [B][nth]
-    d2 *const XLH = XL + B * nth;       // L(half-step Phi)   [B][nth]
-    d2 *const EU = XLH + B * nth;       // Pi^n of each group's last column       [G][nth]
-    d2 *const HU = EU + G * nth;        // half-step Pi of each group's first half node
+    d2 *const XLH = XL;                 // L(half-step Phi)   [B][nth]
+    d2 *const EU = XL + B * nth;        // Pi^n of each group's last column       [G][nth]
+    d2 *const HU = EU;                  // half-step Pi of each group's first half node
     const uint32_t plane = (uint32_t)nr * nth;
     const GLB double *wtab = gptr(A.wt);
     const int reach = A.reach;
@@ -1496,9 +1503,19 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         u[r] = i < nr ? gld_pt<double>(gptr(A.uin), plane, (uint32_t)(i * nth + j)) : zero;
         xput_ghosted<double>(XP + (kg + r) * RS, RS, j, nth, u[r].phi);
     }
-    // radial row of node (or half node) i, wave-uniform: scalar loads
+    // radial row of node (or half node) i, wave-uniform: scalar loads.  The
+    // row of a phase's stage r > 0 is requested only once stage r - 1 has a
+    // result (`after`, through an empty asm): one 32-SGPR row is live at a
+    // time instead of R, which the SGPR file cannot hold besides the launch
+    // arguments (they would be parked in VGPR lanes and read back around
+    // every use).
     auto row = [&](bool half, int i) {
         const int iu = __builtin_amdgcn_readfirstlane(i);
+        return (const CNS double *)(half ? A.rh : A.rf) + iu * kRadRow;
+    };
+    auto row_after = [&](bool half, int i, double after) {
+        int iu = __builtin_amdgcn_readfirstlane(i);
+        asm volatile("" : "+s"(iu) : "v"(after));
         return (const CNS double *)(half ? A.rh : A.rf) + iu * kRadRow;
     };
     if (threadIdx.x == 0) stop = 0;
@@ -1542,7 +1559,8 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             const cx<double> ll = r == 0 ? la : xget<double>(XL + (k - 1) * nth, 0, j);
             const cx<double> lc = xget<double>(XL + k * nth, 0, j);
             const Pt<double> bar = pt_avg(left, u[r]);
-            uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), row(true, hc), cs_j, s2_j, hdt);
+            const CNS double *rr = r == 0 ? row(true, hc) : row_after(true, hc, uh[r > 0 ? r - 1 : 0].pi.im);
+            uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
             xput_ghosted<double>(XH + k * RS, RS, j, nth, uh[r].phi);
         }
         __syncthreads();
@@ -1558,6 +1576,7 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         xput<double>(HU + g * nth, 0, j, uh[0].pi);
         if (g == 0 && has_l) slab_signal(slab_flag(A, seg, 1, wv), tag, j);
         __syncthreads();
+        double prev = 0.0;                  // (orders the row loads, see row_after)
         // 4. stage 2 at the nodes c0 + kg + r
         Pt<double> ub = zero;
         cx<double> lb = zero.phi;
@@ -1577,8 +1596,10 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             const Pt<double> &right = r == R - 1 ? ub : uh[r < R - 1 ? r + 1 : 0];
             const cx<double> lr = r == R - 1 ? lb : xget<double>(XLH + (k + 1) * nth, 0, j);
             const cx<double> lc = xget<double>(XLH + k * nth, 0, j);
+            const CNS double *rr = r == 0 ? row(false, ic) : row_after(false, ic, prev);
             const Pt<double> un = lw_stage_row(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr),
-                                               row(false, ic), cs_j, s2_j, dt);
+                                               rr, cs_j, s2_j, dt);
+            prev = un.pi.im;
             u[r] = (i == 0 || i >= nr - 1) ? zero : un;
             xput_ghosted<double>(XP + k * RS, RS, j, nth, u[r].phi);
         }

@@ -23,9 +23,9 @@ hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, cons
 }
 
 // ---- slab sweep (lw_slab_kernel)
-template <int NT, int R>
+template <int NT, int R, int NTH>
 hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
-    const void *f = (const void *)lw_slab_kernel<NT, R>;
+    const void *f = (const void *)lw_slab_kernel<NT, R, NTH>;
     if (mode == 0) {
         SlabArgs arg = *a;
         void *args[] = {&arg};
@@ -36,23 +36,33 @@ hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStr
     return e;
 }
 
-template <int NT>
-hipError_t slab_nt(int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
+template <int NT, int NTH>
+hipError_t slab_r(int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
     switch (r) {
-        case 1: return slab_one<NT, 1>(mode, lds, a, nblocks, stream, per_cu);
-        case 2: return slab_one<NT, 2>(mode, lds, a, nblocks, stream, per_cu);
-        case 4: return slab_one<NT, 4>(mode, lds, a, nblocks, stream, per_cu);
+        case 1: return slab_one<NT, 1, NTH>(mode, lds, a, nblocks, stream, per_cu);
+        case 2: return slab_one<NT, 2, NTH>(mode, lds, a, nblocks, stream, per_cu);
+        case 4: return slab_one<NT, 4, NTH>(mode, lds, a, nblocks, stream, per_cu);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t slab_f64(int nt, int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream,
-                    int *per_cu) {
+template <int NTH>
+hipError_t slab_nt(int nt, int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream,
+                   int *per_cu) {
     switch (nt) {
-        case 128: return slab_nt<128>(r, mode, lds, a, nblocks, stream, per_cu);
-        case 256: return slab_nt<256>(r, mode, lds, a, nblocks, stream, per_cu);
-        case 512: return slab_nt<512>(r, mode, lds, a, nblocks, stream, per_cu);
-        case 1024: return slab_nt<1024>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 256: return slab_r<256, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 512: return slab_r<512, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 1024: return slab_r<1024, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t slab_f64(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
+                    hipStream_t stream, int *per_cu) {
+    switch (nth) {
+        case 64: return slab_nt<64>(nt, r, mode, lds, a, nblocks, stream, per_cu);
+        case 128: return slab_nt<128>(nt, r, mode, lds, a, nblocks, stream, per_cu);
+        case 256: return slab_nt<256>(nt, r, mode, lds, a, nblocks, stream, per_cu);
         default: return hipErrorInvalidValue;
     }
 }

@@ -340,17 +340,13 @@ int plan_slab(const Batch &h, Batch &b) {
     if (!I.onfly || I.injected)
         return fail(TEUK_ENOTSUP, "the slab sweep needs per-point coefficients (not stored or injected planes)");
     const int nth = I.g.n_theta, nr = I.g.n_r;
-    if (nth % 64 != 0 || nth > 1024) return fail(TEUK_ENOTSUP, "the slab sweep needs n_theta a multiple of 64, at most 1024");
+    if (nth != 64 && nth != 128 && nth != 256) return fail(TEUK_ENOTSUP, "the slab sweep is built for n_theta 64, 128 and 256");
     if (b.fuse != 1)
         return fail(TEUK_EINVAL, "the slab sweep runs a call's steps in one launch: steps per launch must be 1");
-    // default block: the largest of 128..1024 threads that is a multiple of
-    // n_theta and at most 4 n_theta
-    int nt = b.nt_req;
-    for (int c = 1024; !nt && c >= 128; c /= 2)
-        if (c % nth == 0 && c <= 4 * nth) nt = c;
-    if (!nt) return fail(TEUK_ENOTSUP, "slab sweep: no block of 128..1024 threads is a multiple of n_theta");
-    if (nt < 128 || nt < nth || nt % nth != 0)
-        return fail(TEUK_EINVAL, "slab sweep: block must be 128..1024 threads and a multiple of n_theta");
+    // default block: 4 n_theta threads (four groups)
+    const int nt = b.nt_req ? b.nt_req : 4 * nth;
+    if (nt < 256 || nt < nth || nt % nth != 0)
+        return fail(TEUK_EINVAL, "slab sweep: block must be 256, 512 or 1024 threads and a multiple of n_theta");
     const int G = nt / nth;
     int dev = 0, cus = 0, coop = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -385,7 +381,7 @@ int plan_slab(const Batch &h, Batch &b) {
             continue;
         }
         int per_cu = 0;
-        e = lwk::slab_f64(nt, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
+        e = lwk::slab_f64(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
         if (e != hipSuccess) return hip_fail(e, "slab sweep: occupancy");
         const int ns = (nr + cand - 1) / cand;
         if ((long)per_cu * cus < ns) {
@@ -877,7 +873,7 @@ hipError_t slab_launch(Batch &b, int parity, int ns) {
     a.dt = I.dt[0];
     hipError_t e = hipSuccess;
     if (b.slab_fault) e = hipMemsetD32Async((hipDeviceptr_t)b.slab_err, 1, 1, b.stream);
-    if (e == hipSuccess) e = lwk::slab_f64(b.nt, b.slab_r, 0, b.lds, &a, b.slab_nseg, b.stream, nullptr);
+    if (e == hipSuccess) e = lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, 0, b.lds, &a, b.slab_nseg, b.stream, nullptr);
     b.slab_base += ns;
     return e;
 }
