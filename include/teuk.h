@@ -44,6 +44,7 @@
  *   TEUK_FAULT=slab-abort every wait of every slab-sweep launch gives up at
  *                         once (the kernel ends early, the handle fails with
  *                         TEUK_EDEVICE at its next synchronising call);
+ *   TEUK_SLAB_COOPERATIVE slab-sweep launches are cooperative launches;
  *   TEUK_NO_SCALAR_ROWS   the FP64 wide sweeps stage the radial coefficient
  *                         rows in LDS even where scalar loads could serve them
  *                         (same results, bitwise).
@@ -168,8 +169,12 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
  *   instance, n_theta 64, 128 or 256, one step per launch setting
  *   (teuk_set_fuse 1); block 256, 512 or 1024 threads and a multiple of
  *   n_theta (default 4 n_theta), and segcols 1, 2 or 4 times block /
- *   n_theta; every block must be
- *   resident at once (cooperative launch), else TEUK_ENOTSUP.  With the
+ *   n_theta; the device must hold every block at once (occupancy times
+ *   compute units at least the number of segments), else TEUK_ENOTSUP.
+ *   Launched plainly after that check (TEUK_SLAB_COOPERATIVE: cooperatively,
+ *   the runtime then guarantees that all blocks run together).  Work on other
+ *   streams or processes that holds compute units can delay blocks of a plain
+ *   launch; the waits are bounded, so that shows as TEUK_EDEVICE, not a hang.  With the
  *   default block a segment length that does not fit is replaced by the
  *   shortest that does (teuk_set_launch with a block asks for exactly that
  *   shape).  No graphs are

@@ -78,10 +78,12 @@ hipError_t wide_f64(int nt, int run, int cmode, int tm, int ns, size_t lds, cons
 // The persistent slab sweep (lw_slab_kernel, FP64 with per-point
 // coefficients, one instance): nt threads in {256, 512, 1024} = nt / nth
 // groups, nth = n_theta in {64, 128, 256}, r in {1, 2, 4} columns per lane
-// (hipErrorInvalidValue otherwise).  mode 0: launch the nblocks blocks
-// cooperatively (all resident at once, or an error) on `stream` with `lds`
-// bytes of dynamic LDS; mode 1: enable `lds` bytes for the kernel and store in
-// *per_cu how many of its blocks one compute unit holds.
+// (hipErrorInvalidValue otherwise).  mode 0: launch the nblocks blocks on
+// `stream` with `lds` bytes of dynamic LDS (the caller has checked that the
+// device holds them all at once); mode 2: the same as a cooperative launch
+// (the runtime guarantees residency or fails); mode 1: enable `lds` bytes for
+// the kernel and store in *per_cu how many of its blocks one compute unit
+// holds.
 hipError_t slab_f64(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
                     hipStream_t stream, int *per_cu);
 hipError_t wide_dd(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,

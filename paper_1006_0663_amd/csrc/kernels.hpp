@@ -1365,7 +1365,9 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 // can rewrite a buffer two steps later only after it has waited for data this
 // block produces after reading it.
 //
-// Every block must be resident at once (the host launches cooperatively).
+// Every block must be resident at once: the host launches only after checking
+// that the device holds them all (occupancy x compute units), and can launch
+// cooperatively, which makes the runtime guarantee it.
 // A wait polls at most `spin` times; a wave that gives up sets *err, every
 // other wait returns as soon as it sees *err, and the blocks leave the step
 // loop after the next barrier, so the kernel always ends; the host turns a

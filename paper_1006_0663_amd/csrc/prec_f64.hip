@@ -27,6 +27,10 @@ template <int NT, int R, int NTH>
 hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
     const void *f = (const void *)lw_slab_kernel<NT, R, NTH>;
     if (mode == 0) {
+        lw_slab_kernel<NT, R, NTH><<<nblocks, NT, lds, stream>>>(*a);
+        return hipGetLastError();
+    }
+    if (mode == 2) {
         SlabArgs arg = *a;
         void *args[] = {&arg};
         return hipLaunchCooperativeKernel(f, dim3(nblocks), dim3(NT), args, (unsigned)lds, stream);

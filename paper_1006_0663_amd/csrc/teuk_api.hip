@@ -163,6 +163,7 @@ struct Batch {
     int *slab_err = nullptr;
     long long slab_base = 0;
     bool slab_fault = false;         // TEUK_FAULT=slab-abort: every wait of every launch gives up
+    bool slab_coop = std::getenv("TEUK_SLAB_COOPERATIVE") != nullptr;   // cooperative launches
 };
 
 void free_slab(Batch &b) {
@@ -353,7 +354,7 @@ int plan_slab(const Batch &h, Batch &b) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
     if (e != hipSuccess) return hip_fail(e, "slab sweep: device attributes");
-    if (!coop) return fail(TEUK_ENOTSUP, "slab sweep: the device does not launch cooperatively");
+    if (h.slab_coop && !coop) return fail(TEUK_ENOTSUP, "slab sweep: the device does not launch cooperatively");
     // the requested segment length; with the default block, one that does not
     // fit is replaced by the shortest that does (1, 2 or 4 columns per lane)
     std::vector<int> segs{b.seg_req};
@@ -873,7 +874,8 @@ hipError_t slab_launch(Batch &b, int parity, int ns) {
     a.dt = I.dt[0];
     hipError_t e = hipSuccess;
     if (b.slab_fault) e = hipMemsetD32Async((hipDeviceptr_t)b.slab_err, 1, 1, b.stream);
-    if (e == hipSuccess) e = lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, 0, b.lds, &a, b.slab_nseg, b.stream, nullptr);
+    if (e == hipSuccess)
+        e = lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, b.slab_coop ? 2 : 0, b.lds, &a, b.slab_nseg, b.stream, nullptr);
     b.slab_base += ns;
     return e;
 }

@@ -49,6 +49,7 @@ C2 = inputs.C2
 # 256; other spin weights and negative m.
 CASES = [
     ("headline-16x512", C2, 16, 512, [100, 3]),
+    ("headline-16x1024", C2, 16, 1024, [20, 20, 7]),
     ("ragged-1000x64", C2.with_(n_r=1000, n_theta=64), 16, 512, [37, 64, 1]),
     ("r1-200x64", C2.with_(n_r=200, n_theta=64), 4, 256, [50]),
     ("one-segment-16x64", C2.with_(n_r=16, n_theta=64), 16, 256, [20]),
@@ -95,6 +96,22 @@ def test_slab_matches_oracle(label, w, seg, block):
     err = rel_linf(got, oracle_run(w, fields, nsteps, processes=8))
     _note("  rel Linf = %.3e" % err)
     assert err <= TOL_FP64
+
+
+def test_slab_cooperative_launch_is_bitwise(monkeypatch):
+    """TEUK_SLAB_COOPERATIVE (read when the handle is created) launches the
+    same kernel cooperatively: same bits."""
+    w = C2.with_(n_r=700, n_theta=128)
+    fields = inputs.initial_fields(w)
+    a = _handle(w, fields, T.SWEEP_SLAB, 16, 1024)
+    monkeypatch.setenv("TEUK_SLAB_COOPERATIVE", "1")
+    b = _handle(w, fields, T.SWEEP_SLAB, 16, 1024)
+    monkeypatch.delenv("TEUK_SLAB_COOPERATIVE")
+    a.step(33)
+    b.step(33)
+    assert _same(a.fields(), b.fields())
+    a.close()
+    b.close()
 
 
 def test_slab_observer_series_equals_wide_sweep():
