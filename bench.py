@@ -30,7 +30,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 #  traffic: HBM bytes per launch of the headline kernel, FETCH_SIZE and
 #    WRITE_SIZE in KiB; a 256 MiB device copy reads FETCH_SIZE 131,093 KiB
 #    (scale 2.0) and WRITE_SIZE 262,144 KiB (scale 1.0).  Key: (sweep,
-#    segcols, block, steps per launch).
+#    segcols, block, steps per launch); the slab sweep's launch runs the
+#    whole timed call (20 steps in the default run).
 #  fp64_flops_hw: FP64 operations per update as the hardware counts them
 #    (SQ_INSTS_VALU_FLOPS_FP64 = 2 FMA + ADD + MUL wave instructions, x 64
 #    lanes, per launch, over the updates of that launch): unlike the operation
@@ -41,10 +42,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 #    from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 in the same way.  Key as
 #    fp64_flops_hw.
 MEASURED = {
-    "source": "53de0516d14d", "fetch_scale": 2.0, "write_scale": 1.0,
-    "traffic": {(2, 16, 512, 4): (9888.8, 16384.0)},
+    "source": "995f963277db", "fetch_scale": 2.0, "write_scale": 1.0,
+    "traffic": {(3, 16, 1024, 20): (44451.0, 90509.5)},
     "fp64_flops_hw": {
-        ("fp64-4096x128", 2, 16, 512, 4): 373.2,
+        ("fp64-4096x128", 3, 16, 1024, 1): 256.0,
         ("fp64-256x32", 1, 4, 512, 4): 959.5,
         ("dd-256x32", 1, 2, 256, 2): 5066.0,
         ("dd-1024x64", 1, 4, 512, 2): 2880.7,
@@ -53,7 +54,7 @@ MEASURED = {
         ("qd-4096x128", 1, 16, 256, 1): 14260.5,
     },
     "fp64_mix": {
-        ("fp64-4096x128", 2, 16, 512, 4): (40.2, 60.6, 134.7, 2.9),
+        ("fp64-4096x128", 3, 16, 1024, 1): (28.0, 42.0, 92.0, 2.0),
         ("fp64-256x32", 1, 4, 512, 4): (101.5, 153.8, 348.5, 7.2),
         ("dd-256x32", 1, 2, 256, 2): (3074.0, 336.0, 828.0, 0.0),
         ("dd-1024x64", 1, 4, 512, 2): (1771.3, 191.9, 458.8, 0.0),
