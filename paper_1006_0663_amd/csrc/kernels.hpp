@@ -1386,14 +1386,15 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 struct SlabArgs {
     const double *uin;
     double *uout;
-    const double *rf, *rh, *trig, *wt;
-    double *xbuf;                       // [2 parities][2: E1, E2][nseg][6][n_theta]
+    const double *rf, *rh, *trig, *wt;  // FP64 radial rows, theta factors; angular weights (all types)
+    const double *ch, *cf;              // multiword: stored coefficient planes (half nodes, nodes)
+    double *xbuf;                       // [2 parities][2: E1, E2][nseg][6 W][n_theta]
     unsigned long long *flags;          // [nseg][2: E1, E2][n_theta / 64], kSlabFlagPad apart
     int *err;
     long long base;                     // tag of the step before the launch's first
     long long spin;                     // polls before a wait gives up
     int nr, nth, nseg, reach, nsteps;
-    double hdt, dt;
+    double hdt[kMaxWords], dt[kMaxWords];   // dt / 2 and dt, W words
 };
 constexpr int kSlabFlagPad = 16;        // 128 bytes between flags
 
@@ -1426,15 +1427,27 @@ __device__ __forceinline__ void slab_st(double *p, double v) {
 __device__ __forceinline__ double slab_ld(double *p) {
     return __builtin_bit_cast(double, __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
+template <class T> __device__ __forceinline__ void slab_st_t(double *p, int nth, const T &v) {
+#pragma unroll
+    for (int w = 0; w < words_of<T>::value; ++w) slab_st(p + w * nth, mp_word(v, w));
+}
+template <class T> __device__ __forceinline__ T slab_ld_t(double *p, int nth) {
+    T v;
+#pragma unroll
+    for (int w = 0; w < words_of<T>::value; ++w) mp_set_word(v, w, slab_ld(p + w * nth));
+    return v;
+}
 
-// Store a row's six doubles (component-major, n_theta apart).
-__device__ __forceinline__ void slab_put(double *dst, int nth, int j, const Pt<double> &u, const cx<double> &l) {
-    slab_st(dst + 0 * nth + j, u.phi.re);
-    slab_st(dst + 1 * nth + j, u.phi.im);
-    slab_st(dst + 2 * nth + j, u.pi.re);
-    slab_st(dst + 3 * nth + j, u.pi.im);
-    slab_st(dst + 4 * nth + j, l.re);
-    slab_st(dst + 5 * nth + j, l.im);
+// Store a row's six values (component-major, W words each, n_theta apart).
+template <class T>
+__device__ __forceinline__ void slab_put(double *dst, int nth, int j, const Pt<T> &u, const cx<T> &l) {
+    constexpr int W = words_of<T>::value;
+    slab_st_t(dst + (0 * W) * nth + j, nth, u.phi.re);
+    slab_st_t(dst + (1 * W) * nth + j, nth, u.phi.im);
+    slab_st_t(dst + (2 * W) * nth + j, nth, u.pi.re);
+    slab_st_t(dst + (3 * W) * nth + j, nth, u.pi.im);
+    slab_st_t(dst + (4 * W) * nth + j, nth, l.re);
+    slab_st_t(dst + (5 * W) * nth + j, nth, l.im);
 }
 // After the wave's slab_put: wait until its stores have completed, then lane
 // 0 sets the flag to `tag`.
@@ -1445,30 +1458,38 @@ __device__ __forceinline__ void slab_signal(unsigned long long *flag, unsigned l
     if ((j & 63) == 0) __hip_atomic_store(flag, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void slab_take(double *src, int nth, int j, Pt<double> &u, cx<double> &l) {
-    u.phi = {slab_ld(src + 0 * nth + j), slab_ld(src + 1 * nth + j)};
-    u.pi = {slab_ld(src + 2 * nth + j), slab_ld(src + 3 * nth + j)};
-    l = {slab_ld(src + 4 * nth + j), slab_ld(src + 5 * nth + j)};
+template <class T>
+__device__ __forceinline__ void slab_take(double *src, int nth, int j, Pt<T> &u, cx<T> &l) {
+    constexpr int W = words_of<T>::value;
+    u.phi = {slab_ld_t<T>(src + (0 * W) * nth + j, nth), slab_ld_t<T>(src + (1 * W) * nth + j, nth)};
+    u.pi = {slab_ld_t<T>(src + (2 * W) * nth + j, nth), slab_ld_t<T>(src + (3 * W) * nth + j, nth)};
+    l = {slab_ld_t<T>(src + (4 * W) * nth + j, nth), slab_ld_t<T>(src + (5 * W) * nth + j, nth)};
 }
 
-// LDS bytes of the slab kernel: Phi^n and half-step Phi of the B columns
-// (ghosted), L of every column, Pi of one column per group (L(Phi^n) and the
-// half step's L share one array, as do Pi^n and the half-step Pi: each is
-// dead before the other is written)
-MPA size_t slab_lds_bytes(int nt, int nth, int r) {
-    const int G = nt / nth, B = G * r, RS = nth + 2 * kMaxReach;
-    return sizeof(d2) * (2 * (size_t)B * RS + (size_t)B * nth + (size_t)G * nth);
+// LDS bytes of the slab kernel for W words per real: Phi^n and half-step Phi
+// of the B columns (ghosted), L of every column, Pi of one column per group
+// (L(Phi^n) and the half step's L share one array, as do Pi^n and the
+// half-step Pi: each is dead before the other is written); a complex value
+// takes max(1, W) 16-byte chunks
+MPA size_t slab_lds_bytes(int nt, int nth, int r, int words) {
+    const int G = nt / nth, B = G * r, RS = nth + 2 * kMaxReach, CH = words == 1 ? 1 : words;
+    return sizeof(d2) * CH * (2 * (size_t)B * RS + (size_t)B * nth + (size_t)G * nth);
 }
 
 // NT threads = G groups of NTH (= n_theta, a multiple of 64) lanes; R
 // columns per lane.  A lane keeps u^n and the half step of its R columns in
 // registers; the angular operator of every column goes to LDS, where the lane
 // and its neighbours read it back.  n_theta is a template parameter so that
-// every LDS offset is an instruction immediate.
-template <int NT, int R, int NTH>
+// every LDS offset is an instruction immediate.  Coefficients: FP64 rebuilds
+// them per point from radial rows (scalar loads); double-double loads the
+// stored planes of its R columns once into registers (they do not change
+// between steps) and keeps its angular weights in registers too.
+template <class T, int NT, int R, int NTH>
 __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
     constexpr int RM = kMaxReach;
+    constexpr int W = words_of<T>::value, CH = W == 1 ? 1 : W;
     static_assert(NT % NTH == 0 && NTH % 64 == 0, "groups of whole wavefronts");
+    static_assert(W <= 2, "FP64 and double-double");
     extern __shared__ d2 xs[];
     __shared__ int stop;
     constexpr int nth = NTH, G = NT / nth, B = G * R, RS = nth + 2 * RM;
@@ -1480,34 +1501,60 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
     // (XL and XLH share their array, as do EU and HU: phase 1 writes XL and
     // EU, phase 2 reads them, phase 3 writes XLH and HU, phase 4 reads them,
     // and a barrier separates each of these)
-    d2 *const XP = xs;                  // Phi^n              [B][RS]
-    d2 *const XH = XP + B * RS;         // half-step Phi      [B][RS]
-    d2 *const XL = XH + B * RS;         // L(Phi^n)           [B][nth]
-    d2 *const XLH = XL;                 // L(half-step Phi)   [B][nth]
-    d2 *const EU = XL + B * nth;        // Pi^n of each group's last column       [G][nth]
+    d2 *const XP = xs;                  // Phi^n              [B][CH][RS]
+    d2 *const XH = XP + B * CH * RS;    // half-step Phi      [B][CH][RS]
+    d2 *const XL = XH + B * CH * RS;    // L(Phi^n)           [B][CH][nth]
+    d2 *const XLH = XL;                 // L(half-step Phi)   [B][CH][nth]
+    d2 *const EU = XL + B * CH * nth;   // Pi^n of each group's last column       [G][CH][nth]
     d2 *const HU = EU;                  // half-step Pi of each group's first half node
-    const uint32_t plane = (uint32_t)nr * nth;
+    const uint32_t plane = (uint32_t)nr * nth, hplane = (uint32_t)(nr - 1) * nth;
     const GLB double *wtab = gptr(A.wt);
     const int reach = A.reach;
-    const double hdt = A.hdt, dt = A.dt;
-    const double cs_j = gptr(A.trig)[j], s2_j = gptr(A.trig)[nth + j];
+    const T hdt = from_words<T>(A.hdt), dt = from_words<T>(A.dt);
+    double cs_j = 0.0, s2_j = 0.0;
+    if constexpr (W == 1) {
+        cs_j = gptr(A.trig)[j];
+        s2_j = gptr(A.trig)[nth + j];
+    }
+    // angular weights of row j (taps -RM..RM, zero beyond the reach)
     double wreg[2 * RM + 1];
+    T wmp[W == 2 ? 2 * RM + 1 : 1];
 #pragma unroll
     for (int k = 0; k < 2 * RM + 1; ++k) {
         const int kk = k - RM;
-        wreg[k] = (kk >= -reach && kk <= reach) ? wtab[(uint32_t)((kk + reach) * nth + j)] : 0.0;
+        const bool on = kk >= -reach && kk <= reach;
+        if constexpr (W == 1)
+            wreg[k] = on ? wtab[(uint32_t)((kk + reach) * nth + j)] : 0.0;
+        else
+            wmp[k] = on ? gld<T>(wtab + (uint32_t)((kk + reach) * W * nth), (uint32_t)nth, (uint32_t)j) : mp_from<T>(0.0);
     }
-    const Pt<double> zero = {{0.0, 0.0}, {0.0, 0.0}};
-    Pt<double> u[R];
+    const T z = mp_from<T>(0.0);
+    const Pt<T> zero = {{z, z}, {z, z}};
+    // multiword: the coefficients of the lane's half nodes and nodes, once
+    // (clamped indices where a node or half node does not exist; unused)
+    T cfh[W == 1 ? 1 : R][8], cff[W == 1 ? 1 : R][8];
+    if constexpr (W > 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t ih = (uint32_t)(min(max(c0 + kg + r - 1, 0), nr - 2) * nth + j);
+            const uint32_t in = (uint32_t)(min(c0 + kg + r, nr - 1) * nth + j);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                cfh[r][q] = gld<T>(gptr(A.ch) + q * W * hplane, hplane, ih);
+                cff[r][q] = gld<T>(gptr(A.cf) + q * W * plane, plane, in);
+            }
+        }
+    }
+    Pt<T> u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = c0 + kg + r;
-        u[r] = i < nr ? gld_pt<double>(gptr(A.uin), plane, (uint32_t)(i * nth + j)) : zero;
-        xput_ghosted<double>(XP + (kg + r) * RS, RS, j, nth, u[r].phi);
+        u[r] = i < nr ? gld_pt<T>(gptr(A.uin), plane, (uint32_t)(i * nth + j)) : zero;
+        xput_ghosted<T>(XP + (kg + r) * CH * RS, RS, j, nth, u[r].phi);
     }
-    // radial row of node (or half node) i, wave-uniform: scalar loads.  The
-    // row of a phase's stage r > 0 is requested only once stage r - 1 has a
-    // result (`after`, through an empty asm): one 32-SGPR row is live at a
+    // FP64: radial row of node (or half node) i, wave-uniform: scalar loads.
+    // The row of a phase's stage r > 0 is requested only once stage r - 1 has
+    // a result (`after`, through an empty asm): one 32-SGPR row is live at a
     // time instead of R, which the SGPR file cannot hold besides the launch
     // arguments (they would be parked in VGPR lanes and read back around
     // every use).
@@ -1524,46 +1571,51 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
     __syncthreads();
     for (int s = 0; s < A.nsteps; ++s) {
         const unsigned long long tag = (unsigned long long)(A.base + s + 1);
-        const size_t xo = (size_t)(tag & 1) * 2 * A.nseg * 6 * nth;
-        double *const x1 = A.xbuf + xo, *const x2 = A.xbuf + xo + (size_t)A.nseg * 6 * nth;
+        const size_t xo = (size_t)(tag & 1) * 2 * A.nseg * 6 * W * nth;
+        double *const x1 = A.xbuf + xo, *const x2 = A.xbuf + xo + (size_t)A.nseg * 6 * W * nth;
         // 1. L(Phi^n) to LDS, the group's last column first (the last group
         //    publishes it as E1 before the other columns); Pi^n of that column
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int r = R - 1 - q;
-            const cx<double> l = stencil_ghosted<double>(XP + (kg + r) * RS, RS, j, nth, reach, wtab, wreg);
-            xput<double>(XL + (kg + r) * nth, 0, j, l);
-            if (q == 0 && g == G - 1 && has_r) slab_put(x1 + (size_t)seg * 6 * nth, nth, j, u[R - 1], l);
+            const cx<T> l = stencil_ghosted<T>(XP + (kg + r) * CH * RS, RS, j, nth, reach, wtab, wreg,
+                                               W == 2 ? wmp : nullptr);
+            xput<T>(XL + (kg + r) * CH * nth, nth, j, l);
+            if (q == 0 && g == G - 1 && has_r) slab_put(x1 + (size_t)seg * 6 * W * nth, nth, j, u[R - 1], l);
         }
-        xput<double>(EU + g * nth, 0, j, u[R - 1].pi);
+        xput<T>(EU + g * CH * nth, nth, j, u[R - 1].pi);
         if (g == G - 1 && has_r) slab_signal(slab_flag(A, seg, 0, wv), tag, j);
         __syncthreads();
         // 2. stage 1 at the half nodes c0 + kg + r - 1/2 (half index c0 + kg + r - 1)
-        Pt<double> ua = zero;
-        cx<double> la = zero.phi;
+        Pt<T> ua = zero;
+        cx<T> la = zero.phi;
         if (g > 0) {
-            ua.phi = xget<double>(XP + (kg - 1) * RS, RS, RM + j);
-            ua.pi = xget<double>(EU + (g - 1) * nth, 0, j);
-            la = xget<double>(XL + (kg - 1) * nth, 0, j);
+            ua.phi = xget<T>(XP + (kg - 1) * CH * RS, RS, RM + j);
+            ua.pi = xget<T>(EU + (g - 1) * CH * nth, nth, j);
+            la = xget<T>(XL + (kg - 1) * CH * nth, nth, j);
         } else if (has_l) {
             if (slab_wait(slab_flag(A, seg - 1, 0, wv), tag, A.err, A.spin))
-                slab_take(x1 + (size_t)(seg - 1) * 6 * nth, nth, j, ua, la);
+                slab_take(x1 + (size_t)(seg - 1) * 6 * W * nth, nth, j, ua, la);
             else
                 stop = 1;
         }
-        Pt<double> uh[R];
+        Pt<T> uh[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             // (half node -1/2 of the first segment and those past the right
             // boundary do not exist: computed with clamped rows, never used)
             const int k = kg + r, hc = min(max(c0 + k - 1, 0), nr - 2);
-            const Pt<double> &left = r == 0 ? ua : u[r > 0 ? r - 1 : 0];
-            const cx<double> ll = r == 0 ? la : xget<double>(XL + (k - 1) * nth, 0, j);
-            const cx<double> lc = xget<double>(XL + k * nth, 0, j);
-            const Pt<double> bar = pt_avg(left, u[r]);
-            const CNS double *rr = r == 0 ? row(true, hc) : row_after(true, hc, uh[r > 0 ? r - 1 : 0].pi.im);
-            uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
-            xput_ghosted<double>(XH + k * RS, RS, j, nth, uh[r].phi);
+            const Pt<T> &left = r == 0 ? ua : u[r > 0 ? r - 1 : 0];
+            const cx<T> ll = r == 0 ? la : xget<T>(XL + (k - 1) * CH * nth, nth, j);
+            const cx<T> lc = xget<T>(XL + k * CH * nth, nth, j);
+            const Pt<T> bar = pt_avg(left, u[r]);
+            if constexpr (W == 1) {
+                const CNS double *rr = r == 0 ? row(true, hc) : row_after(true, hc, uh[r > 0 ? r - 1 : 0].pi.im);
+                uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
+            } else {
+                uh[r] = lw_stage(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), cfh[r], hdt);
+            }
+            xput_ghosted<T>(XH + k * CH * RS, RS, j, nth, uh[r].phi);
         }
         __syncthreads();
         if (stop) break;
@@ -1571,39 +1623,44 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         //    (group 0 publishes it as E2 before the others); half-step Pi of it
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const cx<double> lh = stencil_ghosted<double>(XH + (kg + r) * RS, RS, j, nth, reach, wtab, wreg);
-            xput<double>(XLH + (kg + r) * nth, 0, j, lh);
-            if (r == 0 && g == 0 && has_l) slab_put(x2 + (size_t)seg * 6 * nth, nth, j, uh[0], lh);
+            const cx<T> lh = stencil_ghosted<T>(XH + (kg + r) * CH * RS, RS, j, nth, reach, wtab, wreg,
+                                                W == 2 ? wmp : nullptr);
+            xput<T>(XLH + (kg + r) * CH * nth, nth, j, lh);
+            if (r == 0 && g == 0 && has_l) slab_put(x2 + (size_t)seg * 6 * W * nth, nth, j, uh[0], lh);
         }
-        xput<double>(HU + g * nth, 0, j, uh[0].pi);
+        xput<T>(HU + g * CH * nth, nth, j, uh[0].pi);
         if (g == 0 && has_l) slab_signal(slab_flag(A, seg, 1, wv), tag, j);
         __syncthreads();
-        double prev = 0.0;                  // (orders the row loads, see row_after)
         // 4. stage 2 at the nodes c0 + kg + r
-        Pt<double> ub = zero;
-        cx<double> lb = zero.phi;
+        Pt<T> ub = zero;
+        cx<T> lb = zero.phi;
         if (g < G - 1) {
-            ub.phi = xget<double>(XH + (kg + R) * RS, RS, RM + j);
-            ub.pi = xget<double>(HU + (g + 1) * nth, 0, j);
-            lb = xget<double>(XLH + (kg + R) * nth, 0, j);
+            ub.phi = xget<T>(XH + (kg + R) * CH * RS, RS, RM + j);
+            ub.pi = xget<T>(HU + (g + 1) * CH * nth, nth, j);
+            lb = xget<T>(XLH + (kg + R) * CH * nth, nth, j);
         } else if (has_r) {
             if (slab_wait(slab_flag(A, seg + 1, 1, wv), tag, A.err, A.spin))
-                slab_take(x2 + (size_t)(seg + 1) * 6 * nth, nth, j, ub, lb);
+                slab_take(x2 + (size_t)(seg + 1) * 6 * W * nth, nth, j, ub, lb);
             else
                 stop = 1;
         }
+        double prev = 0.0;                  // (orders the FP64 row loads, see row_after)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int k = kg + r, i = c0 + k, ic = min(i, nr - 1);
-            const Pt<double> &right = r == R - 1 ? ub : uh[r < R - 1 ? r + 1 : 0];
-            const cx<double> lr = r == R - 1 ? lb : xget<double>(XLH + (k + 1) * nth, 0, j);
-            const cx<double> lc = xget<double>(XLH + k * nth, 0, j);
-            const CNS double *rr = r == 0 ? row(false, ic) : row_after(false, ic, prev);
-            const Pt<double> un = lw_stage_row(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr),
-                                               rr, cs_j, s2_j, dt);
-            prev = un.pi.im;
+            const Pt<T> &right = r == R - 1 ? ub : uh[r < R - 1 ? r + 1 : 0];
+            const cx<T> lr = r == R - 1 ? lb : xget<T>(XLH + (k + 1) * CH * nth, nth, j);
+            const cx<T> lc = xget<T>(XLH + k * CH * nth, nth, j);
+            Pt<T> un;
+            if constexpr (W == 1) {
+                const CNS double *rr = r == 0 ? row(false, ic) : row_after(false, ic, prev);
+                un = lw_stage_row(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), rr, cs_j, s2_j, dt);
+                prev = un.pi.im;
+            } else {
+                un = lw_stage(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), cff[r], dt);
+            }
             u[r] = (i == 0 || i >= nr - 1) ? zero : un;
-            xput_ghosted<double>(XP + k * RS, RS, j, nth, u[r].phi);
+            xput_ghosted<T>(XP + k * CH * RS, RS, j, nth, u[r].phi);
         }
         __syncthreads();
         if (stop) break;

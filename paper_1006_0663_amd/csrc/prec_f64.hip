@@ -22,52 +22,8 @@ hipError_t fp64_planes(int nr, int nth, const double *rf, const double *rh, cons
     return hipGetLastError();
 }
 
-// ---- slab sweep (lw_slab_kernel)
-template <int NT, int R, int NTH>
-hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
-    const void *f = (const void *)lw_slab_kernel<NT, R, NTH>;
-    if (mode == 0) {
-        lw_slab_kernel<NT, R, NTH><<<nblocks, NT, lds, stream>>>(*a);
-        return hipGetLastError();
-    }
-    if (mode == 2) {
-        SlabArgs arg = *a;
-        void *args[] = {&arg};
-        return hipLaunchCooperativeKernel(f, dim3(nblocks), dim3(NT), args, (unsigned)lds, stream);
-    }
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, NT, lds);
-    return e;
-}
-
-template <int NT, int NTH>
-hipError_t slab_r(int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
-    switch (r) {
-        case 1: return slab_one<NT, 1, NTH>(mode, lds, a, nblocks, stream, per_cu);
-        case 2: return slab_one<NT, 2, NTH>(mode, lds, a, nblocks, stream, per_cu);
-        case 4: return slab_one<NT, 4, NTH>(mode, lds, a, nblocks, stream, per_cu);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <int NTH>
-hipError_t slab_nt(int nt, int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream,
-                   int *per_cu) {
-    switch (nt) {
-        case 256: return slab_r<256, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
-        case 512: return slab_r<512, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
-        case 1024: return slab_r<1024, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 hipError_t slab_f64(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
                     hipStream_t stream, int *per_cu) {
-    switch (nth) {
-        case 64: return slab_nt<64>(nt, r, mode, lds, a, nblocks, stream, per_cu);
-        case 128: return slab_nt<128>(nt, r, mode, lds, a, nblocks, stream, per_cu);
-        case 256: return slab_nt<256>(nt, r, mode, lds, a, nblocks, stream, per_cu);
-        default: return hipErrorInvalidValue;
-    }
+    return slab_launch<double>(nt, nth, r, mode, lds, a, nblocks, stream, per_cu);
 }
 }  // namespace lwk

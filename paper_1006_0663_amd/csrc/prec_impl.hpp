@@ -335,4 +335,58 @@ hipError_t wide_launch(int nt, int run, int cmode, int tm, int ns, size_t lds, c
     }
 }
 
+// ---- slab sweep (lw_slab_kernel): nt in {256, 512, 1024}, nth in {64, 128,
+// 256}, r in {1, 2, 4} (FP64) or {1, 2} (double-double)
+template <class T, int NT, int R, int NTH>
+hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
+    const void *f = (const void *)lw_slab_kernel<T, NT, R, NTH>;
+    if (mode == 0) {
+        lw_slab_kernel<T, NT, R, NTH><<<nblocks, NT, lds, stream>>>(*a);
+        return hipGetLastError();
+    }
+    if (mode == 2) {
+        SlabArgs arg = *a;
+        void *args[] = {&arg};
+        return hipLaunchCooperativeKernel(f, dim3(nblocks), dim3(NT), args, (unsigned)lds, stream);
+    }
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, NT, lds);
+    return e;
+}
+
+template <class T, int NT, int NTH>
+hipError_t slab_r(int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
+    switch (r) {
+        case 1: return slab_one<T, NT, 1, NTH>(mode, lds, a, nblocks, stream, per_cu);
+        case 2: return slab_one<T, NT, 2, NTH>(mode, lds, a, nblocks, stream, per_cu);
+        case 4:
+            if constexpr (words_of<T>::value == 1) return slab_one<T, NT, 4, NTH>(mode, lds, a, nblocks, stream, per_cu);
+            break;
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class T, int NTH>
+hipError_t slab_nt(int nt, int r, int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream,
+                   int *per_cu) {
+    switch (nt) {
+        case 256: return slab_r<T, 256, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 512: return slab_r<T, 512, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
+        case 1024: return slab_r<T, 1024, NTH>(r, mode, lds, a, nblocks, stream, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T>
+hipError_t slab_launch(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
+                       hipStream_t stream, int *per_cu) {
+    switch (nth) {
+        case 64: return slab_nt<T, 64>(nt, r, mode, lds, a, nblocks, stream, per_cu);
+        case 128: return slab_nt<T, 128>(nt, r, mode, lds, a, nblocks, stream, per_cu);
+        case 256: return slab_nt<T, 256>(nt, r, mode, lds, a, nblocks, stream, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace lwk

@@ -337,9 +337,9 @@ int wide_cols(int c0, int c1, int nr, int ns) {
 int plan_slab(const Batch &h, Batch &b) {
     if (b.inst.size() != 1) return fail(TEUK_ENOTSUP, "the slab sweep advances a single instance");
     const Instance &I = b.inst[0];
-    if (b.words != 1) return fail(TEUK_ENOTSUP, "the slab sweep is built for FP64");
-    if (!I.onfly || I.injected)
-        return fail(TEUK_ENOTSUP, "the slab sweep needs per-point coefficients (not stored or injected planes)");
+    if (b.words != 1 && b.words != 2) return fail(TEUK_ENOTSUP, "the slab sweep is built for FP64 and double-double");
+    if (b.words == 1 && (!I.onfly || I.injected))
+        return fail(TEUK_ENOTSUP, "the FP64 slab sweep needs per-point coefficients (not stored or injected planes)");
     const int nth = I.g.n_theta, nr = I.g.n_r;
     if (nth != 64 && nth != 128 && nth != 256) return fail(TEUK_ENOTSUP, "the slab sweep is built for n_theta 64, 128 and 256");
     if (b.fuse != 1)
@@ -356,24 +356,27 @@ int plan_slab(const Batch &h, Batch &b) {
     if (e != hipSuccess) return hip_fail(e, "slab sweep: device attributes");
     if (h.slab_coop && !coop) return fail(TEUK_ENOTSUP, "slab sweep: the device does not launch cooperatively");
     // the requested segment length; with the default block, one that does not
-    // fit is replaced by the shortest that does (1, 2 or 4 columns per lane)
+    // fit is replaced by the shortest that does (1, 2 or 4 columns per lane;
+    // double-double 1 or 2)
+    const int max_r = b.words == 1 ? 4 : 2;
     std::vector<int> segs{b.seg_req};
     if (!b.nt_req)
-        for (int r : {1, 2, 4}) segs.push_back(G * r);
+        for (int r = 1; r <= max_r; r *= 2) segs.push_back(G * r);
     int seg = 0, r = 0, nseg = 0;
     size_t lds = 0;
     std::string why;
     int why_rc = TEUK_OK;
     for (int cand : segs) {
         const int rc_ = cand / G;
-        if (cand % G != 0 || (rc_ != 1 && rc_ != 2 && rc_ != 4)) {
+        if (cand % G != 0 || (rc_ != 1 && rc_ != 2 && rc_ != 4) || rc_ > max_r) {
             if (why.empty()) {
-                why = "slab sweep: segcols must be 1, 2 or 4 times block / n_theta";
+                why = b.words == 1 ? "slab sweep: segcols must be 1, 2 or 4 times block / n_theta"
+                                   : "double-double slab sweep: segcols must be 1 or 2 times block / n_theta";
                 why_rc = TEUK_EINVAL;
             }
             continue;
         }
-        const size_t l = lwk::slab_lds_bytes(nt, nth, rc_);
+        const size_t l = lwk::slab_lds_bytes(nt, nth, rc_, b.words);
         if (l > (size_t)device_lds_limit()) {
             if (why.empty()) {
                 why = "slab sweep: launch shape needs more LDS than the device has";
@@ -382,7 +385,8 @@ int plan_slab(const Batch &h, Batch &b) {
             continue;
         }
         int per_cu = 0;
-        e = lwk::slab_f64(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
+        e = b.words == 1 ? lwk::slab_f64(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu)
+                         : lwk::slab_dd(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
         if (e != hipSuccess) return hip_fail(e, "slab sweep: occupancy");
         const int ns = (nr + cand - 1) / cand;
         if ((long)per_cu * cus < ns) {
@@ -401,7 +405,7 @@ int plan_slab(const Batch &h, Batch &b) {
         break;
     }
     if (!seg) return fail(why_rc, why);
-    const size_t nx = 2 * 2 * (size_t)nseg * 6 * nth, nf = (size_t)nseg * 2 * (nth / 64) * lwk::kSlabFlagPad;
+    const size_t nx = 2 * 2 * (size_t)nseg * 6 * b.words * nth, nf = (size_t)nseg * 2 * (nth / 64) * lwk::kSlabFlagPad;
     e = hipMalloc((void **)&b.slab_x, nx * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&b.slab_flags, nf * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void **)&b.slab_err, sizeof(int));
@@ -416,7 +420,7 @@ int plan_slab(const Batch &h, Batch &b) {
     b.nt = nt;
     b.segcols = seg;
     b.lds = lds;
-    b.cmode = 2;
+    b.cmode = b.words == 1 ? 2 : 0;
     b.tm = 0;
     b.slab_r = r;
     b.slab_nseg = nseg;
@@ -860,6 +864,8 @@ hipError_t slab_launch(Batch &b, int parity, int ns) {
     a.rh = I.rh;
     a.trig = I.trig;
     a.wt = I.wt;
+    a.ch = I.ch;
+    a.cf = I.cf;
     a.xbuf = b.slab_x;
     a.flags = b.slab_flags;
     a.err = b.slab_err;
@@ -870,12 +876,14 @@ hipError_t slab_launch(Batch &b, int parity, int ns) {
     a.nseg = b.slab_nseg;
     a.reach = I.reach;
     a.nsteps = ns;
-    a.hdt = I.hdt[0];
-    a.dt = I.dt[0];
+    std::memcpy(a.hdt, I.hdt, sizeof a.hdt);
+    std::memcpy(a.dt, I.dt, sizeof a.dt);
     hipError_t e = hipSuccess;
     if (b.slab_fault) e = hipMemsetD32Async((hipDeviceptr_t)b.slab_err, 1, 1, b.stream);
+    const int mode = b.slab_coop ? 2 : 0;
     if (e == hipSuccess)
-        e = lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, b.slab_coop ? 2 : 0, b.lds, &a, b.slab_nseg, b.stream, nullptr);
+        e = b.words == 1 ? lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr)
+                         : lwk::slab_dd(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr);
     b.slab_base += ns;
     return e;
 }

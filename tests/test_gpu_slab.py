@@ -15,9 +15,6 @@ from parity_util import oracle_run, rel_linf
 
 pytestmark = pytest.mark.gpu
 
-TOL_FP64 = 1e-12
-
-
 def _note(msg):
     print(msg, flush=True)
     sys.stdout.flush()
@@ -56,6 +53,11 @@ CASES = [
     ("nth256-600x256", C2.with_(n_r=600, n_theta=256), 4, 1024, [9, 12]),
     ("s1-m-2-333x64", C2.with_(n_r=333, n_theta=64, s=1, m=-2, a_over_M=0.95), 8, 256, [7, 30]),
     ("s0-m0-a0-257x128", C2.with_(n_r=257, n_theta=128, s=0, m=0, a_over_M=0.0), 8, 512, [41]),
+    # double-double (coefficients held in registers, one or two columns per lane)
+    ("dd-1024x64", inputs.C3_PARITY, 4, 256, [13, 20]),
+    ("dd-ragged-333x64-s1-m-2", inputs.C3_PARITY.with_(n_r=333, s=1, m=-2, a_over_M=0.95), 8, 256, [7, 30]),
+    ("dd-300x128", C2.with_(n_r=300, words=2), 4, 512, [11]),
+    ("dd-one-segment-8x64", inputs.C3_PARITY.with_(n_r=8), 8, 256, [9]),
 ]
 
 
@@ -80,7 +82,10 @@ ORACLE_CASES = [
     ("fp64-m2-61x64", inputs.C1.with_(n_r=61, n_theta=64, rstar_min=60.0, rstar_max=150.0, words=1), 4, 256),
     ("fp64-s2-m-2-45x64", inputs.C1.with_(n_r=45, n_theta=64, rstar_min=70.0, rstar_max=140.0, s=2, m=-2,
                                           a_over_M=0.9, words=1), 8, 256),
+    ("dd-m3-a0.99-45x64", inputs.C4.with_(n_r=45, n_theta=64, rstar_min=60.0, rstar_max=150.0, m=3, words=2),
+     4, 256),
 ]
+TOL = {1: 1e-12, 2: 1e-28}
 
 
 @pytest.mark.parametrize("label,w,seg,block", ORACLE_CASES, ids=[c[0] for c in ORACLE_CASES])
@@ -95,7 +100,7 @@ def test_slab_matches_oracle(label, w, seg, block):
     h.close()
     err = rel_linf(got, oracle_run(w, fields, nsteps, processes=8))
     _note("  rel Linf = %.3e" % err)
-    assert err <= TOL_FP64
+    assert err <= TOL[w.words]
 
 
 def test_slab_cooperative_launch_is_bitwise(monkeypatch):
@@ -191,8 +196,17 @@ def test_slab_refusals_and_fallbacks():
     assert h.sweep != T.SWEEP_SLAB
     h.step(5)
     h.close()
-    # multiword, n_theta not a multiple of 64, batches
-    for ww, code in ((w.with_(words=2), T.TEUK_ENOTSUP), (w.with_(n_theta=32), T.TEUK_ENOTSUP)):
+    # quad-double, n_theta not 64, 128 or 256, double-double with four columns per lane, batches
+    with pytest.raises(T.TeukError) as ex:
+        g = _handle(w.with_(words=2), inputs.initial_fields(w.with_(words=2)))
+        try:
+            g.set_sweep(T.SWEEP_SLAB)
+            g.set_launch(16, 256)
+        finally:
+            g.close()
+    assert ex.value.code == T.TEUK_EINVAL
+    for ww, code in ((w.with_(words=4), T.TEUK_ENOTSUP), (w.with_(n_theta=32), T.TEUK_ENOTSUP),
+                     (w.with_(n_theta=192), T.TEUK_ENOTSUP)):
         g = _handle(ww, inputs.initial_fields(ww))
         with pytest.raises(T.TeukError) as ex:
             g.set_sweep(T.SWEEP_SLAB)
