@@ -1349,15 +1349,15 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 //      the end of the phase); Pi^n of that column to LDS.
 //   2. Stage 1 at the R half nodes left of the columns.  The first takes u^n
 //      and L left of the group from the group to the left, or for group 0
-//      from E1 of the left neighbour (waiting for its flag).  Half-step Phi to
-//      LDS.
+//      from E1 of the left neighbour (waiting for its flag, after the other
+//      half nodes).  Half-step Phi to LDS.
 //   3. L of the half steps to LDS (group 0 stores its first half node as E2
 //      right away, flag at the end of the phase); half-step Pi of the group's
 //      first half node to LDS.
 //   4. Stage 2 at the R nodes.  The last takes the half step right of it from
 //      the group to the right, or for the last group from E2 of the right
-//      neighbour (waiting).  Radial boundary nodes are reset to zero;
-//      Phi^{n+1} to LDS.
+//      neighbour (waiting, after the other nodes).  Radial boundary nodes are
+//      reset to zero; Phi^{n+1} to LDS.
 // Each operand is the value the other sweeps use and every point takes the
 // same operations in the same order, so the results are bitwise equal to
 // theirs; no column is computed twice and no launch boundary falls between
@@ -1586,36 +1586,42 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         xput<T>(EU + g * CH * nth, nth, j, u[R - 1].pi);
         if (g == G - 1 && has_r) slab_signal(slab_flag(A, seg, 0, wv), tag, j);
         __syncthreads();
-        // 2. stage 1 at the half nodes c0 + kg + r - 1/2 (half index c0 + kg + r - 1)
-        Pt<T> ua = zero;
-        cx<T> la = zero.phi;
-        if (g > 0) {
-            ua.phi = xget<T>(XP + (kg - 1) * CH * RS, RS, RM + j);
-            ua.pi = xget<T>(EU + (g - 1) * CH * nth, nth, j);
-            la = xget<T>(XL + (kg - 1) * CH * nth, nth, j);
-        } else if (has_l) {
-            if (slab_wait(slab_flag(A, seg - 1, 0, wv), tag, A.err, A.spin))
-                slab_take(x1 + (size_t)(seg - 1) * 6 * W * nth, nth, j, ua, la);
-            else
-                stop = 1;
-        }
+        // 2. stage 1 at the half nodes c0 + kg + r - 1/2 (half index c0 + kg + r - 1),
+        //    r = 1..R-1 first: only r = 0 needs the values left of the group,
+        //    which group 0 waits for (E1), so the wait follows the others
         Pt<T> uh[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
+        double prev1 = 0.0;                 // (orders the FP64 row loads, see row_after)
+        auto stage1 = [&](int r, const Pt<T> &left, const cx<T> &ll) {
             // (half node -1/2 of the first segment and those past the right
             // boundary do not exist: computed with clamped rows, never used)
             const int k = kg + r, hc = min(max(c0 + k - 1, 0), nr - 2);
-            const Pt<T> &left = r == 0 ? ua : u[r > 0 ? r - 1 : 0];
-            const cx<T> ll = r == 0 ? la : xget<T>(XL + (k - 1) * CH * nth, nth, j);
             const cx<T> lc = xget<T>(XL + k * CH * nth, nth, j);
             const Pt<T> bar = pt_avg(left, u[r]);
             if constexpr (W == 1) {
-                const CNS double *rr = r == 0 ? row(true, hc) : row_after(true, hc, uh[r > 0 ? r - 1 : 0].pi.im);
+                const CNS double *rr = r == R - 1 && R > 1 ? row(true, hc) : row_after(true, hc, prev1);
                 uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
+                prev1 = uh[r].pi.im;
             } else {
                 uh[r] = lw_stage(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), cfh[r], hdt);
             }
             xput_ghosted<T>(XH + k * CH * RS, RS, j, nth, uh[r].phi);
+        };
+#pragma unroll
+        for (int r = R - 1; r >= 1; --r) stage1(r, u[r - 1], xget<T>(XL + (kg + r - 1) * CH * nth, nth, j));
+        {
+            Pt<T> ua = zero;
+            cx<T> la = zero.phi;
+            if (g > 0) {
+                ua.phi = xget<T>(XP + (kg - 1) * CH * RS, RS, RM + j);
+                ua.pi = xget<T>(EU + (g - 1) * CH * nth, nth, j);
+                la = xget<T>(XL + (kg - 1) * CH * nth, nth, j);
+            } else if (has_l) {
+                if (slab_wait(slab_flag(A, seg - 1, 0, wv), tag, A.err, A.spin))
+                    slab_take(x1 + (size_t)(seg - 1) * 6 * W * nth, nth, j, ua, la);
+                else
+                    stop = 1;
+            }
+            stage1(0, ua, la);
         }
         __syncthreads();
         if (stop) break;
@@ -1631,25 +1637,12 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         xput<T>(HU + g * CH * nth, nth, j, uh[0].pi);
         if (g == 0 && has_l) slab_signal(slab_flag(A, seg, 1, wv), tag, j);
         __syncthreads();
-        // 4. stage 2 at the nodes c0 + kg + r
-        Pt<T> ub = zero;
-        cx<T> lb = zero.phi;
-        if (g < G - 1) {
-            ub.phi = xget<T>(XH + (kg + R) * CH * RS, RS, RM + j);
-            ub.pi = xget<T>(HU + (g + 1) * CH * nth, nth, j);
-            lb = xget<T>(XLH + (kg + R) * CH * nth, nth, j);
-        } else if (has_r) {
-            if (slab_wait(slab_flag(A, seg + 1, 1, wv), tag, A.err, A.spin))
-                slab_take(x2 + (size_t)(seg + 1) * 6 * W * nth, nth, j, ub, lb);
-            else
-                stop = 1;
-        }
+        // 4. stage 2 at the nodes c0 + kg + r, r = 0..R-2 first: only r = R-1
+        //    needs the half step right of the group, which the last group
+        //    waits for (E2), so the wait follows the others
         double prev = 0.0;                  // (orders the FP64 row loads, see row_after)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
+        auto stage2 = [&](int r, const Pt<T> &right, const cx<T> &lr) {
             const int k = kg + r, i = c0 + k, ic = min(i, nr - 1);
-            const Pt<T> &right = r == R - 1 ? ub : uh[r < R - 1 ? r + 1 : 0];
-            const cx<T> lr = r == R - 1 ? lb : xget<T>(XLH + (k + 1) * CH * nth, nth, j);
             const cx<T> lc = xget<T>(XLH + k * CH * nth, nth, j);
             Pt<T> un;
             if constexpr (W == 1) {
@@ -1661,6 +1654,23 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             }
             u[r] = (i == 0 || i >= nr - 1) ? zero : un;
             xput_ghosted<T>(XP + k * CH * RS, RS, j, nth, u[r].phi);
+        };
+#pragma unroll
+        for (int r = 0; r < R - 1; ++r) stage2(r, uh[r + 1], xget<T>(XLH + (kg + r + 1) * CH * nth, nth, j));
+        {
+            Pt<T> ub = zero;
+            cx<T> lb = zero.phi;
+            if (g < G - 1) {
+                ub.phi = xget<T>(XH + (kg + R) * CH * RS, RS, RM + j);
+                ub.pi = xget<T>(HU + (g + 1) * CH * nth, nth, j);
+                lb = xget<T>(XLH + (kg + R) * CH * nth, nth, j);
+            } else if (has_r) {
+                if (slab_wait(slab_flag(A, seg + 1, 1, wv), tag, A.err, A.spin))
+                    slab_take(x2 + (size_t)(seg + 1) * 6 * W * nth, nth, j, ub, lb);
+                else
+                    stop = 1;
+            }
+            stage2(R - 1, ub, lb);
         }
         __syncthreads();
         if (stop) break;
