@@ -166,11 +166,12 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
  *   global memory and flags, so no column is computed twice and no launch
  *   falls between steps (Sec. "Teukolsky Code": the step needs one
  *   neighbour on each side in r*).  One instance, FP64 with per-point
- *   coefficients or double-double (whose stored coefficients the kernel
- *   holds in registers), n_theta 64, 128 or 256, one step per launch setting
- *   (teuk_set_fuse 1); block 256, 512 or 1024 threads and a multiple of
- *   n_theta (default 4 n_theta), and segcols 1, 2 or 4 (double-double: 1 or
- *   2) times block / n_theta; the device must hold every block at once (occupancy times
+ *   coefficients, double-double (whose stored coefficients the kernel holds
+ *   in registers) or quad-double (stored coefficients loaded per stage),
+ *   n_theta 64, 128 or 256, one step per launch setting (teuk_set_fuse 1);
+ *   block 256, 512 or 1024 threads and a multiple of n_theta (default
+ *   4 n_theta), and segcols 1, 2 or 4 (multiword: 1 or 2) times block /
+ *   n_theta; the device must hold every block at once (occupancy times
  *   compute units at least the number of segments), else TEUK_ENOTSUP.
  *   Launched plainly after that check (TEUK_SLAB_COOPERATIVE: cooperatively,
  *   the runtime then guarantees that all blocks run together).  Work on other

@@ -20,7 +20,7 @@ SEGMENT, WIDE, WIDE2, SLAB = 0, 1, 2, 3
 # at once) takes a call's steps in one launch; shapes whose blocks do not all
 # fit on the device are refused by the library and skipped.  Double-double
 # slab shapes hold their coefficients in registers (one or two columns per
-# lane).
+# lane); quad-double ones load them per stage (one column per lane).
 CANDIDATES = {
     1: [(WIDE, s, b, 1) for b in (128, 256, 512) for s in (4, 6, 8, 12, 16, 24)]
        + [(WIDE2, s, b, 1) for b in (128, 256, 512) for s in (4, 6, 8, 10, 16, 22)]
@@ -33,7 +33,8 @@ CANDIDATES = {
        + [(SEGMENT, 2, 0, 1), (SEGMENT, 2, 128, 1)]
        + [(WIDE, s, b, 2) for b in (256, 512) for s in (2, 4)] + [(WIDE, s, 512, 4) for s in (4, 8)]
        + [(SLAB, s, b, 1) for b, s in ((256, 4), (256, 8), (512, 4), (512, 8))],
-    4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12, 16)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)],
+    4: [(WIDE, s, b, 1) for b in (128, 256) for s in (2, 4, 6, 8, 12, 16)] + [(SEGMENT, 2, 128, 1), (SEGMENT, 2, 0, 1)]
+       + [(SLAB, s, b, 1) for b, s in ((256, 4), (512, 8), (1024, 16))],
 }
 
 

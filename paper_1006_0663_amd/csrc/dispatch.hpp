@@ -76,9 +76,9 @@ hipError_t wide_f64(int nt, int run, int cmode, int tm, int ns, size_t lds, cons
                     const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,
                     bool attr_only);
 // The persistent slab sweep (lw_slab_kernel, one instance; FP64 with
-// per-point coefficients, or double-double with stored planes): nt threads in
-// {256, 512, 1024} = nt / nth groups, nth = n_theta in {64, 128, 256}, r in
-// {1, 2, 4} (FP64) or {1, 2} (double-double) columns per lane
+// per-point coefficients, or double-double / quad-double with stored planes):
+// nt threads in {256, 512, 1024} = nt / nth groups, nth = n_theta in {64,
+// 128, 256}, r in {1, 2, 4} (FP64) or {1, 2} (multiword) columns per lane
 // (hipErrorInvalidValue otherwise).  mode 0: launch the nblocks blocks on
 // `stream` with `lds` bytes of dynamic LDS (the caller has checked that the
 // device holds them all at once); mode 2: the same as a cooperative launch
@@ -88,6 +88,8 @@ hipError_t wide_f64(int nt, int run, int cmode, int tm, int ns, size_t lds, cons
 hipError_t slab_f64(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
                     hipStream_t stream, int *per_cu);
 hipError_t slab_dd(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
+                   hipStream_t stream, int *per_cu);
+hipError_t slab_qd(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
                    hipStream_t stream, int *per_cu);
 hipError_t wide_dd(int nt, int run, int cmode, int tm, int ns, size_t lds, const WideArgs *one,
                     const InstDev *insts, const WorkItem *items, int nitems, int parity, hipStream_t stream,

@@ -1483,13 +1483,15 @@ MPA size_t slab_lds_bytes(int nt, int nth, int r, int words) {
 // every LDS offset is an instruction immediate.  Coefficients: FP64 rebuilds
 // them per point from radial rows (scalar loads); double-double loads the
 // stored planes of its R columns once into registers (they do not change
-// between steps) and keeps its angular weights in registers too.
+// between steps) and keeps its angular weights in registers too; quad-double
+// (at most two columns per lane) loads a stage's coefficients from the planes
+// and each tap's weight, as the wide sweep does.
 template <class T, int NT, int R, int NTH>
 __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
     constexpr int RM = kMaxReach;
     constexpr int W = words_of<T>::value, CH = W == 1 ? 1 : W;
     static_assert(NT % NTH == 0 && NTH % 64 == 0, "groups of whole wavefronts");
-    static_assert(W <= 2, "FP64 and double-double");
+    static_assert(W != 4 || R <= 2, "quad-double: at most two columns per lane");
     extern __shared__ d2 xs[];
     __shared__ int stop;
     constexpr int nth = NTH, G = NT / nth, B = G * R, RS = nth + 2 * RM;
@@ -1517,6 +1519,7 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         s2_j = gptr(A.trig)[nth + j];
     }
     // angular weights of row j (taps -RM..RM, zero beyond the reach)
+    // (quad-double loads each tap's weight in the stencil, as the wide sweep does)
     double wreg[2 * RM + 1];
     T wmp[W == 2 ? 2 * RM + 1 : 1];
 #pragma unroll
@@ -1525,15 +1528,22 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         const bool on = kk >= -reach && kk <= reach;
         if constexpr (W == 1)
             wreg[k] = on ? wtab[(uint32_t)((kk + reach) * nth + j)] : 0.0;
-        else
+        else if constexpr (W == 2)
             wmp[k] = on ? gld<T>(wtab + (uint32_t)((kk + reach) * W * nth), (uint32_t)nth, (uint32_t)j) : mp_from<T>(0.0);
     }
     const T z = mp_from<T>(0.0);
     const Pt<T> zero = {{z, z}, {z, z}};
-    // multiword: the coefficients of the lane's half nodes and nodes, once
-    // (clamped indices where a node or half node does not exist; unused)
-    T cfh[W == 1 ? 1 : R][8], cff[W == 1 ? 1 : R][8];
-    if constexpr (W > 1) {
+    // double-double: the coefficients of the lane's half nodes and nodes,
+    // once (clamped indices where a node or half node does not exist; unused).
+    // Quad-double loads a stage's eight from the planes when it needs them.
+    T cfh[W == 2 ? R : 1][8], cff[W == 2 ? R : 1][8];
+    auto load_cf = [&](bool half, int i, T *c) {
+        const GLB double *pl = gptr(half ? A.ch : A.cf);
+        const uint32_t pn = half ? hplane : plane;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = gld<T>(pl + q * W * pn, pn, (uint32_t)(i * nth + j));
+    };
+    if constexpr (W == 2) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t ih = (uint32_t)(min(max(c0 + kg + r - 1, 0), nr - 2) * nth + j);
@@ -1601,8 +1611,12 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
                 const CNS double *rr = r == R - 1 && R > 1 ? row(true, hc) : row_after(true, hc, prev1);
                 uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
                 prev1 = uh[r].pi.im;
-            } else {
+            } else if constexpr (W == 2) {
                 uh[r] = lw_stage(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), cfh[r], hdt);
+            } else {
+                T cf[8];
+                load_cf(true, hc, cf);
+                uh[r] = lw_stage(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), cf, hdt);
             }
             xput_ghosted<T>(XH + k * CH * RS, RS, j, nth, uh[r].phi);
         };
@@ -1649,8 +1663,12 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
                 const CNS double *rr = r == 0 ? row(false, ic) : row_after(false, ic, prev);
                 un = lw_stage_row(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), rr, cs_j, s2_j, dt);
                 prev = un.pi.im;
-            } else {
+            } else if constexpr (W == 2) {
                 un = lw_stage(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), cff[r], dt);
+            } else {
+                T cf[8];
+                load_cf(false, ic, cf);
+                un = lw_stage(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), cf, dt);
             }
             u[r] = (i == 0 || i >= nr - 1) ? zero : un;
             xput_ghosted<T>(XP + k * CH * RS, RS, j, nth, u[r].phi);

@@ -336,7 +336,7 @@ hipError_t wide_launch(int nt, int run, int cmode, int tm, int ns, size_t lds, c
 }
 
 // ---- slab sweep (lw_slab_kernel): nt in {256, 512, 1024}, nth in {64, 128,
-// 256}, r in {1, 2, 4} (FP64) or {1, 2} (double-double)
+// 256}, r in {1, 2, 4} (FP64) or {1, 2} (double-double, quad-double)
 template <class T, int NT, int R, int NTH>
 hipError_t slab_one(int mode, size_t lds, const SlabArgs *a, int nblocks, hipStream_t stream, int *per_cu) {
     const void *f = (const void *)lw_slab_kernel<T, NT, R, NTH>;

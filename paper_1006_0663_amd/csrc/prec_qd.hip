@@ -15,4 +15,8 @@ hipError_t wide_qd(int nt, int run, int cmode, int tm, int ns, size_t lds, const
                     bool attr_only) {
     return wide_launch<qd>(nt, run, cmode, tm, ns, lds, one, insts, items, nitems, parity, stream, attr_only);
 }
+hipError_t slab_qd(int nt, int nth, int r, int mode, size_t lds, const SlabArgs *a, int nblocks,
+                   hipStream_t stream, int *per_cu) {
+    return slab_launch<qd>(nt, nth, r, mode, lds, a, nblocks, stream, per_cu);
+}
 }  // namespace lwk

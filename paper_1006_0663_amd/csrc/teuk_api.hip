@@ -337,7 +337,7 @@ int wide_cols(int c0, int c1, int nr, int ns) {
 int plan_slab(const Batch &h, Batch &b) {
     if (b.inst.size() != 1) return fail(TEUK_ENOTSUP, "the slab sweep advances a single instance");
     const Instance &I = b.inst[0];
-    if (b.words != 1 && b.words != 2) return fail(TEUK_ENOTSUP, "the slab sweep is built for FP64 and double-double");
+    // (every precision: FP64, double-double, quad-double)
     if (b.words == 1 && (!I.onfly || I.injected))
         return fail(TEUK_ENOTSUP, "the FP64 slab sweep needs per-point coefficients (not stored or injected planes)");
     const int nth = I.g.n_theta, nr = I.g.n_r;
@@ -357,7 +357,7 @@ int plan_slab(const Batch &h, Batch &b) {
     if (h.slab_coop && !coop) return fail(TEUK_ENOTSUP, "slab sweep: the device does not launch cooperatively");
     // the requested segment length; with the default block, one that does not
     // fit is replaced by the shortest that does (1, 2 or 4 columns per lane;
-    // double-double 1 or 2)
+    // multiword 1 or 2)
     const int max_r = b.words == 1 ? 4 : 2;
     std::vector<int> segs{b.seg_req};
     if (!b.nt_req)
@@ -371,7 +371,7 @@ int plan_slab(const Batch &h, Batch &b) {
         if (cand % G != 0 || (rc_ != 1 && rc_ != 2 && rc_ != 4) || rc_ > max_r) {
             if (why.empty()) {
                 why = b.words == 1 ? "slab sweep: segcols must be 1, 2 or 4 times block / n_theta"
-                                   : "double-double slab sweep: segcols must be 1 or 2 times block / n_theta";
+                                   : "multiword slab sweep: segcols must be 1 or 2 times block / n_theta";
                 why_rc = TEUK_EINVAL;
             }
             continue;
@@ -385,8 +385,9 @@ int plan_slab(const Batch &h, Batch &b) {
             continue;
         }
         int per_cu = 0;
-        e = b.words == 1 ? lwk::slab_f64(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu)
-                         : lwk::slab_dd(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
+        e = b.words == 1   ? lwk::slab_f64(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu)
+            : b.words == 2 ? lwk::slab_dd(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu)
+                           : lwk::slab_qd(nt, nth, rc_, 1, l, nullptr, 0, nullptr, &per_cu);
         if (e != hipSuccess) return hip_fail(e, "slab sweep: occupancy");
         const int ns = (nr + cand - 1) / cand;
         if ((long)per_cu * cus < ns) {
@@ -882,8 +883,9 @@ hipError_t slab_launch(Batch &b, int parity, int ns) {
     if (b.slab_fault) e = hipMemsetD32Async((hipDeviceptr_t)b.slab_err, 1, 1, b.stream);
     const int mode = b.slab_coop ? 2 : 0;
     if (e == hipSuccess)
-        e = b.words == 1 ? lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr)
-                         : lwk::slab_dd(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr);
+        e = b.words == 1   ? lwk::slab_f64(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr)
+            : b.words == 2 ? lwk::slab_dd(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr)
+                           : lwk::slab_qd(b.nt, I.g.n_theta, b.slab_r, mode, b.lds, &a, b.slab_nseg, b.stream, nullptr);
     b.slab_base += ns;
     return e;
 }

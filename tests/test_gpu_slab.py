@@ -58,6 +58,9 @@ CASES = [
     ("dd-ragged-333x64-s1-m-2", inputs.C3_PARITY.with_(n_r=333, s=1, m=-2, a_over_M=0.95), 8, 256, [7, 30]),
     ("dd-300x128", C2.with_(n_r=300, words=2), 4, 512, [11]),
     ("dd-one-segment-8x64", inputs.C3_PARITY.with_(n_r=8), 8, 256, [9]),
+    # quad-double (coefficients loaded per stage, one column per lane)
+    ("qd-2048x64", inputs.C4, 8, 512, [3, 2]),
+    ("qd-ragged-203x64-s-1-m2", inputs.C4.with_(n_r=203, s=-1, m=2, a_over_M=0.6), 4, 256, [4]),
 ]
 
 
@@ -84,8 +87,9 @@ ORACLE_CASES = [
                                           a_over_M=0.9, words=1), 8, 256),
     ("dd-m3-a0.99-45x64", inputs.C4.with_(n_r=45, n_theta=64, rstar_min=60.0, rstar_max=150.0, m=3, words=2),
      4, 256),
+    ("qd-m2-a0.99-37x64", inputs.C4.with_(n_r=37, n_theta=64, rstar_min=60.0, rstar_max=150.0, words=4), 8, 512),
 ]
-TOL = {1: 1e-12, 2: 1e-28}
+TOL = {1: 1e-12, 2: 1e-28, 4: 1e-60}
 
 
 @pytest.mark.parametrize("label,w,seg,block", ORACLE_CASES, ids=[c[0] for c in ORACLE_CASES])
@@ -196,7 +200,7 @@ def test_slab_refusals_and_fallbacks():
     assert h.sweep != T.SWEEP_SLAB
     h.step(5)
     h.close()
-    # quad-double, n_theta not 64, 128 or 256, double-double with four columns per lane, batches
+    # n_theta not 64, 128 or 256, double-double with four columns per lane, batches
     with pytest.raises(T.TeukError) as ex:
         g = _handle(w.with_(words=2), inputs.initial_fields(w.with_(words=2)))
         try:
@@ -205,8 +209,7 @@ def test_slab_refusals_and_fallbacks():
         finally:
             g.close()
     assert ex.value.code == T.TEUK_EINVAL
-    for ww, code in ((w.with_(words=4), T.TEUK_ENOTSUP), (w.with_(n_theta=32), T.TEUK_ENOTSUP),
-                     (w.with_(n_theta=192), T.TEUK_ENOTSUP)):
+    for ww, code in ((w.with_(n_theta=32), T.TEUK_ENOTSUP), (w.with_(n_theta=192), T.TEUK_ENOTSUP)):
         g = _handle(ww, inputs.initial_fields(ww))
         with pytest.raises(T.TeukError) as ex:
             g.set_sweep(T.SWEEP_SLAB)
