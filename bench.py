@@ -42,15 +42,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 #    from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 in the same way.  Key as
 #    fp64_flops_hw.
 MEASURED = {
-    "source": "7a67c93059a4", "fetch_scale": 2.0, "write_scale": 1.0,
-    "traffic": {(3, 16, 1024, 20): (45409.9, 90509.5)},
+    "source": "94af26d035fd", "fetch_scale": 2.0, "write_scale": 1.0,
+    "traffic": {(3, 16, 1024, 20): (45433.1, 90509.5)},
     "fp64_flops_hw": {
         ("fp64-4096x128", 3, 16, 1024, 1): 256.0,
         ("fp64-256x32", 1, 4, 512, 4): 959.5,
         ("dd-256x32", 1, 2, 256, 2): 5066.0,
         ("dd-1024x64", 3, 4, 256, 1): 1604.0,
         ("dd-4096x128", 1, 8, 256, 1): 1829.8,
-        ("qd-2048x64", 1, 4, 128, 1): 17077.4,
+        ("qd-2048x64", 3, 8, 512, 1): 13324.0,
         ("qd-4096x128", 1, 16, 256, 1): 14260.5,
     },
     "fp64_mix": {
@@ -59,7 +59,7 @@ MEASURED = {
         ("dd-256x32", 1, 2, 256, 2): (3074.0, 336.0, 828.0, 0.0),
         ("dd-1024x64", 3, 4, 256, 1): (992.0, 108.0, 252.0, 0.0),
         ("dd-4096x128", 1, 8, 256, 1): (1121.9, 123.0, 292.4, 0.0),
-        ("qd-2048x64", 1, 4, 128, 1): (14249.5, 830.7, 998.6, 0.0),
+        ("qd-2048x64", 3, 8, 512, 1): (11176.0, 636.0, 756.0, 0.0),
         ("qd-4096x128", 1, 16, 256, 1): (11942.7, 684.6, 816.6, 0.0),
     },
 }

@@ -1479,9 +1479,13 @@ int teuk_read_observer(teuk_t *h, long max_records, double *out, long *n_out, lo
     Batch &b = h->b;
     if (int rc = check_ok(b)) return rc;
     if (b.obs_n <= 0) return fail(TEUK_EINVAL, "no observer is set");
-    long long c[3];
+    long long c[3] = {0, 0, 0};
     hipError_t e = hipStreamSynchronize(b.stream);
-    if (e == hipSuccess) e = hipMemcpy(c, b.obs_ctr, sizeof c, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+        // records of a slab launch that ended early are not valid
+        if (int rc = slab_check(b)) return rc;
+        e = hipMemcpy(c, b.obs_ctr, sizeof c, hipMemcpyDeviceToHost);
+    }
     const size_t rec = 1 + 2 * (size_t)b.words * b.obs_n;
     const long held = (long)std::min<long long>(c[1], b.obs_cap);
     const long n = std::min(held, max_records);

@@ -165,10 +165,14 @@ def test_slab_abandoned_wait_is_a_device_error(monkeypatch):
     monkeypatch.setenv("TEUK_FAULT", "slab-abort")
     h = _handle(w, fields, T.SWEEP_SLAB, 8, 256)
     monkeypatch.delenv("TEUK_FAULT")
+    h.set_observer([(100, 5)], every=3, capacity=8)
     h.step(10)                                  # launches; the error shows at the next sync
     with pytest.raises(T.TeukError) as ex:
-        h.fields()
+        h.read_observer()                       # its records are not valid either
     assert ex.value.code == T.TEUK_EDEVICE and "neighbouring block" in str(ex.value)
+    with pytest.raises(T.TeukError) as ex:
+        h.fields()
+    assert ex.value.code == T.TEUK_EDEVICE
     with pytest.raises(T.TeukError):
         h.step(1)                               # failed state is sticky
     h.close()
