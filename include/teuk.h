@@ -176,7 +176,11 @@ int teuk_set_launch(teuk_t *h, int segcols, int block);
  *   Launched plainly after that check (TEUK_SLAB_COOPERATIVE: cooperatively,
  *   the runtime then guarantees that all blocks run together).  Work on other
  *   streams or processes that holds compute units can delay blocks of a plain
- *   launch; the waits are bounded, so that shows as TEUK_EDEVICE, not a hang.  With the
+ *   launch; the waits are bounded, so that shows as TEUK_EDEVICE, not a hang.
+ *   In particular two slab launches running at once on different streams
+ *   (two handles) can each hold part of the device while waiting for blocks
+ *   that cannot start: keep such handles on one stream, or launch
+ *   cooperatively.  With the
  *   default block a segment length that does not fit is replaced by the
  *   shortest that does (teuk_set_launch with a block asks for exactly that
  *   shape).  No graphs are

@@ -119,3 +119,23 @@ def test_issue_ceiling_from_the_instruction_mix(monkeypatch):
     assert bench.issue_ceiling("fma", (1, 4, 256, 1), None)["issue_ceiling_frac"] == 1.0
     assert bench.issue_ceiling("add", (1, 4, 256, 1), None)["issue_ceiling_frac"] == 0.5
     assert bench.issue_ceiling("y", (1, 4, 256, 1), 10.0)["issue_ceiling_frac"] is None
+
+
+def test_slab_shapes_in_the_bench_line():
+    """A slab launch runs the whole timed call (up to the library's 4096 steps
+    per launch); fused shapes their own step count.  The roofline names the
+    kernel instance: columns per lane = segcols / (block / n_theta)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.launch_steps((3, 16, 1024, 1), 20) == 20
+    assert bench.launch_steps((3, 16, 1024, 1), 10000) == 4096
+    assert bench.launch_steps((2, 16, 512, 4), 20) == 4
+    assert bench.kernel_name((3, 16, 1024, 1), 20, 128) == "lw_slab_kernel<1024,2> (persistent, 20 steps per launch)"
+    assert bench.kernel_name((2, 16, 512, 4), 4, 128) == "lw_wide_kernel<double,run 2> (4 steps per launch)"
+    assert bench.SWEEP_NAMES[autotune.SLAB] == "slab"
+
+
+def test_slab_candidates_take_one_step_setting():
+    for words in (1, 2, 4):
+        slab = [c for c in autotune.candidates(words, 64) if c[0] == autotune.SLAB]
+        assert slab and all(c[3] == 1 for c in slab)
