@@ -1467,12 +1467,14 @@ __device__ __forceinline__ void slab_take(double *src, int nth, int j, Pt<T> &u,
 }
 
 // LDS bytes of the slab kernel for W words per real: Phi^n and half-step Phi
-// of the B columns (ghosted), L of every column, Pi of one column per group
-// (L(Phi^n) and the half step's L share one array, as do Pi^n and the
-// half-step Pi: each is dead before the other is written); a complex value
-// takes max(1, W) 16-byte chunks
+// of the B columns (ghosted), L of every column, Pi of one column per group; a
+// complex value takes max(1, W) 16-byte chunks.  L(Phi^n) and the half
+// step's L share one array.  With group-level syncs (W <= 2) it has one slot
+// more per group, and Pi^n and the half-step Pi have arrays of their own;
+// quad-double (block barriers only) shares those too.
 MPA size_t slab_lds_bytes(int nt, int nth, int r, int words) {
     const int G = nt / nth, B = G * r, RS = nth + 2 * kMaxReach, CH = words == 1 ? 1 : words;
+    if (words <= 2) return sizeof(d2) * CH * (2 * (size_t)B * RS + (size_t)(B + G) * nth + 2 * (size_t)G * nth);
     return sizeof(d2) * CH * (2 * (size_t)B * RS + (size_t)B * nth + (size_t)G * nth);
 }
 
@@ -1492,23 +1494,34 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
     constexpr int W = words_of<T>::value, CH = W == 1 ? 1 : W;
     static_assert(NT % NTH == 0 && NTH % 64 == 0, "groups of whole wavefronts");
     static_assert(W != 4 || R <= 2, "quad-double: at most two columns per lane");
+    // DEC: phases 2 -> 3 and 4 -> 1 need only the group's own waves (see below)
+    constexpr bool DEC = W <= 2;
+    constexpr int nth = NTH, G = NT / nth, B = G * R, RS = nth + 2 * RM, WPG = NTH / 64;
     extern __shared__ d2 xs[];
-    __shared__ int stop;
-    constexpr int nth = NTH, G = NT / nth, B = G * R, RS = nth + 2 * RM;
+    __shared__ int stop[2];                 // a wait gave up in phase 2, in phase 4
+    __shared__ unsigned gcnt[G];            // group syncs passed, times the group's waves
     const int nr = A.nr;
     const int g = threadIdx.x / nth, j = threadIdx.x - g * nth, wv = j >> 6;
     const int seg = xcd_segment(blockIdx.x, A.nseg);
     const int c0 = seg * B, kg = g * R;
     const bool has_l = seg > 0, has_r = seg + 1 < A.nseg;
-    // (XL and XLH share their array, as do EU and HU: phase 1 writes XL and
-    // EU, phase 2 reads them, phase 3 writes XLH and HU, phase 4 reads them,
-    // and a barrier separates each of these)
+    // XL and XLH share their array; with block barriers only (quad-double)
+    // so do EU and HU: phase 1 writes XL and EU, phase 2 reads them, phase 3
+    // writes XLH and HU, phase 4 reads them, and a barrier separates each.
+    // With group syncs after phases 2 and 4, a group can write while the
+    // neighbouring groups still read, so what they read must not move: each
+    // group has R + 1 slots of L, XLH of column r in slot r and XL in slot
+    // r + 1 (the next group reads XL of the last column, the previous one
+    // XLH of the first: neither is overwritten before the next block
+    // barrier), and HU is apart from EU.
     d2 *const XP = xs;                  // Phi^n              [B][CH][RS]
     d2 *const XH = XP + B * CH * RS;    // half-step Phi      [B][CH][RS]
-    d2 *const XL = XH + B * CH * RS;    // L(Phi^n)           [B][CH][nth]
-    d2 *const XLH = XL;                 // L(half-step Phi)   [B][CH][nth]
-    d2 *const EU = XL + B * CH * nth;   // Pi^n of each group's last column       [G][CH][nth]
-    d2 *const HU = EU;                  // half-step Pi of each group's first half node
+    d2 *const XL = XH + B * CH * RS;    // L(Phi^n)           [B or G (R + 1)][CH][nth]
+    d2 *const XLH = XL;                 // L(half-step Phi)
+    d2 *const EU = XL + (DEC ? B + G : B) * CH * nth;  // Pi^n of each group's last column  [G][CH][nth]
+    d2 *const HU = DEC ? EU + G * CH * nth : EU;        // half-step Pi of each group's first half node
+    auto sl_L = [](int k) { return DEC ? k + k / R + 1 : k; };     // slot of XL for column k
+    auto sl_LH = [](int k) { return DEC ? k + k / R : k; };        // slot of XLH
     const uint32_t plane = (uint32_t)nr * nth, hplane = (uint32_t)(nr - 1) * nth;
     const GLB double *wtab = gptr(A.wt);
     const int reach = A.reach;
@@ -1577,8 +1590,34 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         asm volatile("" : "+s"(iu) : "v"(after));
         return (const CNS double *)(half ? A.rh : A.rf) + iu * kRadRow;
     };
-    if (threadIdx.x == 0) stop = 0;
+    if (threadIdx.x == 0) stop[0] = stop[1] = 0;
+    if (threadIdx.x < G) gcnt[threadIdx.x] = 0;
     __syncthreads();
+    // Sync of the group's waves: LDS writes before it are seen by the group's
+    // reads after it.  One wave: program order (LDS keeps a wave's accesses in
+    // order; the fences keep the compiler's).  Several: a counter in LDS,
+    // polled at most `spin` times (a wave that gives up sets *err and stop[i]).
+    unsigned gk = 0;
+    auto group_sync = [&](int i) {
+        if constexpr (WPG == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            gk += WPG;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if ((j & 63) == 0) __hip_atomic_fetch_add(&gcnt[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (long long it = 0; __hip_atomic_load(&gcnt[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < gk; ++it) {
+                if (it >= A.spin) {
+                    __hip_atomic_store(A.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    stop[i] = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    };
     for (int s = 0; s < A.nsteps; ++s) {
         const unsigned long long tag = (unsigned long long)(A.base + s + 1);
         const size_t xo = (size_t)(tag & 1) * 2 * A.nseg * 6 * W * nth;
@@ -1590,12 +1629,13 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             const int r = R - 1 - q;
             const cx<T> l = stencil_ghosted<T>(XP + (kg + r) * CH * RS, RS, j, nth, reach, wtab, wreg,
                                                W == 2 ? wmp : nullptr);
-            xput<T>(XL + (kg + r) * CH * nth, nth, j, l);
+            xput<T>(XL + sl_L(kg + r) * CH * nth, nth, j, l);
             if (q == 0 && g == G - 1 && has_r) slab_put(x1 + (size_t)seg * 6 * W * nth, nth, j, u[R - 1], l);
         }
         xput<T>(EU + g * CH * nth, nth, j, u[R - 1].pi);
         if (g == G - 1 && has_r) slab_signal(slab_flag(A, seg, 0, wv), tag, j);
         __syncthreads();
+        if (DEC && stop[1]) break;
         // 2. stage 1 at the half nodes c0 + kg + r - 1/2 (half index c0 + kg + r - 1),
         //    r = 1..R-1 first: only r = 0 needs the values left of the group,
         //    which group 0 waits for (E1), so the wait follows the others
@@ -1605,7 +1645,7 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             // (half node -1/2 of the first segment and those past the right
             // boundary do not exist: computed with clamped rows, never used)
             const int k = kg + r, hc = min(max(c0 + k - 1, 0), nr - 2);
-            const cx<T> lc = xget<T>(XL + k * CH * nth, nth, j);
+            const cx<T> lc = xget<T>(XL + sl_L(k) * CH * nth, nth, j);
             const Pt<T> bar = pt_avg(left, u[r]);
             if constexpr (W == 1) {
                 const CNS double *rr = r == R - 1 && R > 1 ? row(true, hc) : row_after(true, hc, prev1);
@@ -1621,43 +1661,48 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             xput_ghosted<T>(XH + k * CH * RS, RS, j, nth, uh[r].phi);
         };
 #pragma unroll
-        for (int r = R - 1; r >= 1; --r) stage1(r, u[r - 1], xget<T>(XL + (kg + r - 1) * CH * nth, nth, j));
+        for (int r = R - 1; r >= 1; --r) stage1(r, u[r - 1], xget<T>(XL + sl_L(kg + r - 1) * CH * nth, nth, j));
         {
             Pt<T> ua = zero;
             cx<T> la = zero.phi;
             if (g > 0) {
                 ua.phi = xget<T>(XP + (kg - 1) * CH * RS, RS, RM + j);
                 ua.pi = xget<T>(EU + (g - 1) * CH * nth, nth, j);
-                la = xget<T>(XL + (kg - 1) * CH * nth, nth, j);
+                la = xget<T>(XL + sl_L(kg - 1) * CH * nth, nth, j);
             } else if (has_l) {
                 if (slab_wait(slab_flag(A, seg - 1, 0, wv), tag, A.err, A.spin))
                     slab_take(x1 + (size_t)(seg - 1) * 6 * W * nth, nth, j, ua, la);
                 else
-                    stop = 1;
+                    stop[0] = 1;
             }
             stage1(0, ua, la);
         }
-        __syncthreads();
-        if (stop) break;
+        if constexpr (DEC) {
+            group_sync(0);
+        } else {
+            __syncthreads();
+            if (stop[0]) break;
+        }
         // 3. L of the half steps to LDS, the group's first half node first
         //    (group 0 publishes it as E2 before the others); half-step Pi of it
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const cx<T> lh = stencil_ghosted<T>(XH + (kg + r) * CH * RS, RS, j, nth, reach, wtab, wreg,
                                                 W == 2 ? wmp : nullptr);
-            xput<T>(XLH + (kg + r) * CH * nth, nth, j, lh);
+            xput<T>(XLH + sl_LH(kg + r) * CH * nth, nth, j, lh);
             if (r == 0 && g == 0 && has_l) slab_put(x2 + (size_t)seg * 6 * W * nth, nth, j, uh[0], lh);
         }
         xput<T>(HU + g * CH * nth, nth, j, uh[0].pi);
         if (g == 0 && has_l) slab_signal(slab_flag(A, seg, 1, wv), tag, j);
         __syncthreads();
+        if (DEC && stop[0]) break;
         // 4. stage 2 at the nodes c0 + kg + r, r = 0..R-2 first: only r = R-1
         //    needs the half step right of the group, which the last group
         //    waits for (E2), so the wait follows the others
         double prev = 0.0;                  // (orders the FP64 row loads, see row_after)
         auto stage2 = [&](int r, const Pt<T> &right, const cx<T> &lr) {
             const int k = kg + r, i = c0 + k, ic = min(i, nr - 1);
-            const cx<T> lc = xget<T>(XLH + k * CH * nth, nth, j);
+            const cx<T> lc = xget<T>(XLH + sl_LH(k) * CH * nth, nth, j);
             Pt<T> un;
             if constexpr (W == 1) {
                 const CNS double *rr = r == 0 ? row(false, ic) : row_after(false, ic, prev);
@@ -1674,26 +1719,32 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             xput_ghosted<T>(XP + k * CH * RS, RS, j, nth, u[r].phi);
         };
 #pragma unroll
-        for (int r = 0; r < R - 1; ++r) stage2(r, uh[r + 1], xget<T>(XLH + (kg + r + 1) * CH * nth, nth, j));
+        for (int r = 0; r < R - 1; ++r) stage2(r, uh[r + 1], xget<T>(XLH + sl_LH(kg + r + 1) * CH * nth, nth, j));
         {
             Pt<T> ub = zero;
             cx<T> lb = zero.phi;
             if (g < G - 1) {
                 ub.phi = xget<T>(XH + (kg + R) * CH * RS, RS, RM + j);
                 ub.pi = xget<T>(HU + (g + 1) * CH * nth, nth, j);
-                lb = xget<T>(XLH + (kg + R) * CH * nth, nth, j);
+                lb = xget<T>(XLH + sl_LH(kg + R) * CH * nth, nth, j);
             } else if (has_r) {
                 if (slab_wait(slab_flag(A, seg + 1, 1, wv), tag, A.err, A.spin))
                     slab_take(x2 + (size_t)(seg + 1) * 6 * W * nth, nth, j, ub, lb);
                 else
-                    stop = 1;
+                    stop[1] = 1;
             }
             stage2(R - 1, ub, lb);
         }
-        __syncthreads();
-        if (stop) break;
+        if constexpr (DEC) {
+            group_sync(1);
+        } else {
+            __syncthreads();
+            if (stop[1]) break;
+        }
     }
-    if (stop) return;
+    // (with group syncs a wait of the last phase 4 is seen only after a barrier)
+    if constexpr (DEC) __syncthreads();
+    if (stop[0] | stop[1]) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = c0 + kg + r;
