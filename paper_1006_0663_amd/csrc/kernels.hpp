@@ -1343,7 +1343,11 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 //   E2 (to the left neighbour): the half step and its L at the segment's
 //       first half node c0 - 1/2, the right operands of the neighbour's last
 //       node.
-// A step has four phases, each closed by a barrier:
+// A step has four phases.  Phases 1 and 3 end with a block barrier: the next
+// phase reads what the neighbouring groups wrote.  Phases 2 and 4 end with a
+// sync of the group's own waves in FP64 and double-double: the stencil that
+// follows reads only the group's columns (quad-double, short of LDS for the
+// separate slots this needs, closes them with block barriers too):
 //   1. L(Phi^n) of the lane's R columns to LDS (the group's last column
 //      first: the last group stores it as E1 right away and sets the flag at
 //      the end of the phase); Pi^n of that column to LDS.
@@ -1370,8 +1374,11 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 // cooperatively, which makes the runtime guarantee it.
 // A wait polls at most `spin` times; a wave that gives up sets *err, every
 // other wait returns as soon as it sees *err, and the blocks leave the step
-// loop after the next barrier, so the kernel always ends; the host turns a
-// nonzero *err into an error.
+// loop after the next block barrier, so the kernel always ends; the host
+// turns a nonzero *err into an error.  (A wait of phase 2 is checked after
+// the barrier of phase 3, one of phase 4 after that of phase 1: a barrier
+// lies between every check and the next wait that can set the flag, so all
+// waves of a block leave at the same point.)
 //
 // Memory ordering across XCDs (each has its own L2) without cache-wide
 // fences: every exchanged double and every flag is a relaxed atomic access
