@@ -1576,6 +1576,17 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         }
     }
     Pt<T> u[R];
+    // Phi of the lane's columns (and below, of its half nodes) is in LDS for
+    // the stencils.  FP64 and quad-double read it back there where a stage
+    // needs it instead of keeping a second copy in registers for the whole
+    // step (the same bits; fewer spills); double-double, which does not
+    // spill, runs faster with the register copy.
+    constexpr bool PL = W != 2;
+    auto U = [&](int r) {
+        Pt<T> v = u[r];
+        if constexpr (PL) v.phi = xget<T>(XP + (kg + r) * CH * RS, RS, RM + j);
+        return v;
+    };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = c0 + kg + r;
@@ -1637,7 +1648,7 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             const cx<T> l = stencil_ghosted<T>(XP + (kg + r) * CH * RS, RS, j, nth, reach, wtab, wreg,
                                                W == 2 ? wmp : nullptr);
             xput<T>(XL + sl_L(kg + r) * CH * nth, nth, j, l);
-            if (q == 0 && g == G - 1 && has_r) slab_put(x1 + (size_t)seg * 6 * W * nth, nth, j, u[R - 1], l);
+            if (q == 0 && g == G - 1 && has_r) slab_put(x1 + (size_t)seg * 6 * W * nth, nth, j, U(R - 1), l);
         }
         xput<T>(EU + g * CH * nth, nth, j, u[R - 1].pi);
         if (g == G - 1 && has_r) slab_signal(slab_flag(A, seg, 0, wv), tag, j);
@@ -1647,28 +1658,34 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         //    r = 1..R-1 first: only r = 0 needs the values left of the group,
         //    which group 0 waits for (E1), so the wait follows the others
         Pt<T> uh[R];
+        auto H = [&](int r) {
+            Pt<T> v = uh[r];
+            if constexpr (PL) v.phi = xget<T>(XH + (kg + r) * CH * RS, RS, RM + j);
+            return v;
+        };
         double prev1 = 0.0;                 // (orders the FP64 row loads, see row_after)
         auto stage1 = [&](int r, const Pt<T> &left, const cx<T> &ll) {
             // (half node -1/2 of the first segment and those past the right
             // boundary do not exist: computed with clamped rows, never used)
             const int k = kg + r, hc = min(max(c0 + k - 1, 0), nr - 2);
             const cx<T> lc = xget<T>(XL + sl_L(k) * CH * nth, nth, j);
-            const Pt<T> bar = pt_avg(left, u[r]);
+            const Pt<T> ur = U(r);
+            const Pt<T> bar = pt_avg(left, ur);
             if constexpr (W == 1) {
                 const CNS double *rr = r == R - 1 && R > 1 ? row(true, hc) : row_after(true, hc, prev1);
-                uh[r] = lw_stage_row(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
+                uh[r] = lw_stage_row(bar, bar, pt_diff(left, ur), c_avg(ll, lc), rr, cs_j, s2_j, hdt);
                 prev1 = uh[r].pi.im;
             } else if constexpr (W == 2) {
-                uh[r] = lw_stage(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), cfh[r], hdt);
+                uh[r] = lw_stage(bar, bar, pt_diff(left, ur), c_avg(ll, lc), cfh[r], hdt);
             } else {
                 T cf[8];
                 load_cf(true, hc, cf);
-                uh[r] = lw_stage(bar, bar, pt_diff(left, u[r]), c_avg(ll, lc), cf, hdt);
+                uh[r] = lw_stage(bar, bar, pt_diff(left, ur), c_avg(ll, lc), cf, hdt);
             }
             xput_ghosted<T>(XH + k * CH * RS, RS, j, nth, uh[r].phi);
         };
 #pragma unroll
-        for (int r = R - 1; r >= 1; --r) stage1(r, u[r - 1], xget<T>(XL + sl_L(kg + r - 1) * CH * nth, nth, j));
+        for (int r = R - 1; r >= 1; --r) stage1(r, U(r - 1), xget<T>(XL + sl_L(kg + r - 1) * CH * nth, nth, j));
         {
             Pt<T> ua = zero;
             cx<T> la = zero.phi;
@@ -1697,7 +1714,7 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
             const cx<T> lh = stencil_ghosted<T>(XH + (kg + r) * CH * RS, RS, j, nth, reach, wtab, wreg,
                                                 W == 2 ? wmp : nullptr);
             xput<T>(XLH + sl_LH(kg + r) * CH * nth, nth, j, lh);
-            if (r == 0 && g == 0 && has_l) slab_put(x2 + (size_t)seg * 6 * W * nth, nth, j, uh[0], lh);
+            if (r == 0 && g == 0 && has_l) slab_put(x2 + (size_t)seg * 6 * W * nth, nth, j, H(0), lh);
         }
         xput<T>(HU + g * CH * nth, nth, j, uh[0].pi);
         if (g == 0 && has_l) slab_signal(slab_flag(A, seg, 1, wv), tag, j);
@@ -1710,23 +1727,24 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         auto stage2 = [&](int r, const Pt<T> &right, const cx<T> &lr) {
             const int k = kg + r, i = c0 + k, ic = min(i, nr - 1);
             const cx<T> lc = xget<T>(XLH + sl_LH(k) * CH * nth, nth, j);
+            const Pt<T> ur = U(r), hr = H(r);
             Pt<T> un;
             if constexpr (W == 1) {
                 const CNS double *rr = r == 0 ? row(false, ic) : row_after(false, ic, prev);
-                un = lw_stage_row(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), rr, cs_j, s2_j, dt);
+                un = lw_stage_row(ur, pt_avg(hr, right), pt_diff(hr, right), c_avg(lc, lr), rr, cs_j, s2_j, dt);
                 prev = un.pi.im;
             } else if constexpr (W == 2) {
-                un = lw_stage(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), cff[r], dt);
+                un = lw_stage(ur, pt_avg(hr, right), pt_diff(hr, right), c_avg(lc, lr), cff[r], dt);
             } else {
                 T cf[8];
                 load_cf(false, ic, cf);
-                un = lw_stage(u[r], pt_avg(uh[r], right), pt_diff(uh[r], right), c_avg(lc, lr), cf, dt);
+                un = lw_stage(ur, pt_avg(hr, right), pt_diff(hr, right), c_avg(lc, lr), cf, dt);
             }
             u[r] = (i == 0 || i >= nr - 1) ? zero : un;
             xput_ghosted<T>(XP + k * CH * RS, RS, j, nth, u[r].phi);
         };
 #pragma unroll
-        for (int r = 0; r < R - 1; ++r) stage2(r, uh[r + 1], xget<T>(XLH + sl_LH(kg + r + 1) * CH * nth, nth, j));
+        for (int r = 0; r < R - 1; ++r) stage2(r, H(r + 1), xget<T>(XLH + sl_LH(kg + r + 1) * CH * nth, nth, j));
         {
             Pt<T> ub = zero;
             cx<T> lb = zero.phi;
@@ -1755,7 +1773,7 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = c0 + kg + r;
-        if (i < nr) gst_pt(gptr(A.uout), plane, (uint32_t)(i * nth + j), u[r]);
+        if (i < nr) gst_pt(gptr(A.uout), plane, (uint32_t)(i * nth + j), U(r));
     }
 }
 
