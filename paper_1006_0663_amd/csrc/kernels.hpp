@@ -1373,7 +1373,8 @@ __global__ __launch_bounds__(NT) void lw_wide_kernel(const double *wa_uin, doubl
 // that the device holds them all (occupancy x compute units), and can launch
 // cooperatively, which makes the runtime guarantee it.
 // A wait polls at most `spin` times; a wave that gives up sets *err, every
-// other wait returns as soon as it sees *err, and the blocks leave the step
+// other wait whose flag has not arrived returns as soon as it sees *err, and
+// the blocks leave the step
 // loop after the next block barrier, so the kernel always ends; the host
 // turns a nonzero *err into an error.  (A wait of phase 2 is checked after
 // the barrier of phase 3, one of phase 4 after that of phase 1: a barrier
@@ -1411,12 +1412,14 @@ __device__ __forceinline__ unsigned long long *slab_flag(const SlabArgs &A, int 
 
 // Wait (all lanes of a wavefront, same flag) until the flag holds `tag` or
 // later.  false: *err was set, or `spin` polls passed (this wave then sets
-// *err).  The signal fence keeps the compiler from moving the caller's data
-// loads above the poll.
+// *err).  The flag is read first and the error word only while the flag is
+// not there yet: a flag that has arrived costs one round trip to the
+// coherence point, not two.  The signal fence keeps the compiler from moving
+// the caller's data loads above the poll.
 __device__ __forceinline__ bool slab_wait(unsigned long long *flag, unsigned long long tag, int *err, long long spin) {
     for (long long it = 0;; ++it) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tag) break;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         if (it >= spin) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
