@@ -41,9 +41,11 @@
  *
  * Environment (read when a handle is created; for tests):
  *   TEUK_FAULT=alloc      creation fails with TEUK_ENOMEM after validation;
- *   TEUK_FAULT=slab-abort every wait of every slab-sweep launch gives up at
- *                         once (the kernel ends early, the handle fails with
- *                         TEUK_EDEVICE at its next synchronising call);
+ *   TEUK_FAULT=slab-abort every slab-sweep launch starts with its error word
+ *                         set, so the first wait that finds its neighbour's
+ *                         flag missing gives up at once (the kernel ends
+ *                         early, the handle fails with TEUK_EDEVICE at its
+ *                         next synchronising call);
  *   TEUK_SLAB_COOPERATIVE slab-sweep launches are cooperative launches;
  *   TEUK_NO_SCALAR_ROWS   the FP64 wide sweeps stage the radial coefficient
  *                         rows in LDS even where scalar loads could serve them

@@ -156,10 +156,10 @@ def test_slab_host_round_trip_is_bitwise():
 
 
 def test_slab_abandoned_wait_is_a_device_error(monkeypatch):
-    """TEUK_FAULT=slab-abort makes every wait give up at once (set from the
-    host before each launch): the kernel ends early, the next synchronising
-    call reports TEUK_EDEVICE and the handle stays failed; a new handle runs
-    normally afterwards."""
+    """TEUK_FAULT=slab-abort sets the error word from the host before each
+    launch, so the first wait that finds its flag missing gives up at once:
+    the kernel ends early, the next synchronising call reports TEUK_EDEVICE
+    and the handle stays failed; a new handle runs normally afterwards."""
     w = C2.with_(n_r=512, n_theta=64)
     fields = inputs.initial_fields(w)
     monkeypatch.setenv("TEUK_FAULT", "slab-abort")
