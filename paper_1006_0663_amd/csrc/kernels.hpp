@@ -1611,6 +1611,14 @@ __global__ __launch_bounds__(NT) void lw_slab_kernel(SlabArgs A) {
         asm volatile("" : "+s"(iu) : "v"(after));
         return (const CNS double *)(half ? A.rh : A.rf) + iu * kRadRow;
     };
+    // The neighbour exchanges chain the blocks through their edge groups (the
+    // last group's E1, the first group's E2); the other groups have slack.
+    // In FP64 (four wavefronts per SIMD) the edge groups' waves issue first:
+    // the step shortens by about 6 %.  (Double-double, one wavefront per
+    // SIMD in its tuned shape, ran slower with it; quad-double did not change.)
+    if constexpr (W == 1) {
+        if (g == 0 || g == G - 1) __builtin_amdgcn_s_setprio(2);
+    }
     if (threadIdx.x == 0) stop[0] = stop[1] = 0;
     if (threadIdx.x < G) gcnt[threadIdx.x] = 0;
     __syncthreads();
