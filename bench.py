@@ -42,8 +42,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 #    from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 in the same way.  Key as
 #    fp64_flops_hw.
 MEASURED = {
-    "source": "07e167a163cf", "fetch_scale": 2.0, "write_scale": 1.0,
-    "traffic": {(3, 16, 1024, 20): (45439.9, 92557.5)},
+    "source": "0631f1e0dfb0", "fetch_scale": 2.0, "write_scale": 1.0,
+    "traffic": {(3, 16, 1024, 20): (45799.6, 92557.5)},
     "fp64_flops_hw": {
         ("fp64-4096x128", 3, 16, 1024, 1): 256.0,
         ("fp64-256x32", 1, 4, 512, 4): 959.5,
